@@ -1,0 +1,169 @@
+/*
+ * radonlp.h -- C-ABI of the log-polar Radon transform library for AMD MI355X (gfx950).
+ *
+ * The Radon transform R and its adjoint, the back-projection R#, are applied as
+ * periodic convolutions in log-polar coordinates over M angular partitions, following
+ * Andersson, Carlsson and Nikitin, "Fast algorithms and efficient GPU implementations
+ * for the Radon transform and the back-projection operator represented as convolution
+ * operators" (arXiv 1506.00014): sec. 2 (the transform as a log-polar convolution,
+ * eq. logdef, lograd_periodic, Tdef, Radon_all_pb), sec. 3 (kernel coefficients,
+ * eq. exprcoef1; sampling, eq. Xgrid, Polargrid, vrho, Lopolargrid_f,
+ * Lopolargrid_polar), sec. 4 (cubic B-spline interpolation, eq. Bsplineinterp,
+ * wsumn) and sec. 5 (Algorithm 1, fast Radon transform).
+ *
+ * Conventions shared by every entry point
+ *   - Image f: N x N float32, row-major, f[iy][ix] is the value at the node
+ *     x = (-1 + ix*2/N, -1 + iy*2/N) (column index = x1, row index = x2); the object
+ *     is assumed supported in the unit disc.
+ *   - Sinogram g: N_theta x N_s float32, row-major, g[j][k] = R f(theta_j, s_k) with
+ *     theta_j = j*pi/N_theta and s_k = -1 + k*2/N_s, and x . theta = x1 cos + x2 sin.
+ *   - A batch of B slices is B such arrays back to back.
+ *   - All data pointers are DEVICE pointers owned by the caller (for example torch
+ *     tensors).  Inputs and outputs must not overlap.  Outputs are fully overwritten.
+ *   - Every operation is enqueued asynchronously on the given stream; no call
+ *     allocates device memory, synchronises the host, or reads device memory from
+ *     the host, except rl_plan_create (which builds and uploads tables) and
+ *     rl_plan_destroy.  The workspace is caller-provided and must be at least
+ *     rl_workspace_bytes(plan, batch, op) bytes, 256-byte aligned; it may be reused
+ *     by consecutive calls on the same stream but not by concurrent calls.
+ *   - Errors never abort: each call returns an rl_status, and rl_last_error() returns
+ *     a message describing the last failure of the calling thread.
+ */
+#ifndef RADONLP_H
+#define RADONLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RL_OK = 0,
+  RL_ERR_INVALID_ARG = 1,    /* null pointer, negative batch, bad enum, overlapping buffers */
+  RL_ERR_GEOMETRY = 2,       /* geometry violates a bound of the paper or of this library */
+  RL_ERR_WORKSPACE = 3,      /* workspace missing, too small or misaligned */
+  RL_ERR_HIP = 4,            /* a HIP runtime call or kernel launch failed */
+  RL_ERR_UNSUPPORTED_ARCH = 5, /* current device is not gfx950 */
+  RL_ERR_INTERNAL = 6
+} rl_status;
+
+/* Operation selector for rl_workspace_bytes. */
+typedef enum { RL_OP_FWD = 0, RL_OP_ADJ = 1, RL_OP_FBP = 2 } rl_op;
+
+/* Filters of filtered back-projection (sec. 6, eq. ramp).  Only the ramp (Ram-Lak)
+ * filter is implemented; other values return RL_ERR_INVALID_ARG. */
+typedef enum { RL_FILTER_RAMLAK = 0 } rl_filter;
+
+/*
+ * Geometry: every field fixes the discrete operator (changing any of them changes
+ * the result).  Bounds, checked by rl_plan_create:
+ *   n        image side N, even, 8 <= N <= 8192
+ *   n_theta  angles N_theta >= m, <= 16384
+ *   n_s      detector bins N_s, 2 <= N_s <= 4096
+ *   m        angular partitions M >= 3, beta = pi/M (sec. 2)
+ *   n_rho    rho-FFT length, a power of two >= ceil(log a_r / log(1 - 2 a_R / N))
+ *            (sec. 3 eq. vrho), <= 8192
+ *   k_theta  theta-FFT length, a power of two >= 2*ceil(N_theta/M) (sec. 5, the grid
+ *            of size 2 N_theta / M), >= n_own + 4, <= 2048
+ *   r_dec    fine angular oversampling of the log-polar grid: Delta theta / r_dec <=
+ *            2 a_R / N (sec. 3, before eq. Lopolargrid_f), <= 32
+ *   dec_filter  theta low-pass used to go from the fine grid to the coarse one
+ *            (Algorithm 1 step 4; not specified by the paper); 0 = cubic B-spline FIR
+ *            d_n = B(n/r)/r, |n| < 2r, whose response is divided out in the Fourier
+ *            multiplier.  No other value is accepted.
+ */
+typedef struct {
+  int32_t n;
+  int32_t n_theta;
+  int32_t n_s;
+  int32_t m;
+  int32_t n_rho;
+  int32_t k_theta;
+  int32_t r_dec;
+  int32_t dec_filter;
+} rl_geom;
+
+typedef struct rl_plan rl_plan;
+
+/* Fill *out with the default geometry for (n, n_theta, n_s, m): n_rho and k_theta are
+ * the smallest powers of two meeting their bounds, r_dec the smallest integer meeting
+ * its bound, dec_filter = 0.  Host-only; touches no device.  Returns RL_ERR_GEOMETRY if
+ * no valid geometry exists within the limits above. */
+rl_status rl_geom_default(int32_t n, int32_t n_theta, int32_t n_s, int32_t m, rl_geom* out);
+
+/* Validate *geom and build a plan on the current device: partition tables, masks, the
+ * Fourier multiplier H = zeta_hat / (B_hat_rho D_hat_theta) of sec. 3 eq. (exprcoef1)
+ * computed in FP64 by composite Gauss-Legendre quadrature on the device, and FFT
+ * twiddles.  Synchronous and allowed to be slow; not part of any timed path.  The plan
+ * owns its device tables, is immutable after creation and may be used from several
+ * streams at once.  On failure *out is set to NULL. */
+rl_status rl_plan_create(const rl_geom* geom, rl_plan** out);
+
+/* Release a plan and its device tables.  NULL is a no-op.  The caller must make sure
+ * no enqueued work still uses the plan. */
+void rl_plan_destroy(rl_plan* plan);
+
+/* Copy the plan's geometry into *out. */
+rl_status rl_plan_geometry(const rl_plan* plan, rl_geom* out);
+
+/* Workspace bytes needed by one call of `op` on `batch` slices (0 if batch == 0). */
+size_t rl_workspace_bytes(const rl_plan* plan, int32_t batch, rl_op op);
+
+/* R f: Algorithm 1 (sec. 5).  d_img [batch][n][n] -> d_sino [batch][n_theta][n_s].
+ * batch == 0 is a no-op. */
+rl_status radon_fwd(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch,
+                    void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* R# g, the back-projection (sec. 1, eq. def_Radast), computed as the exact weighted
+ * transpose of radon_fwd: for all f, g,  w_S <R f, g> = w_X <f, R# g>  with
+ * w_S = (pi/N_theta)(2/N_s) and w_X = (2/N)^2, i.e. R# = (w_S/w_X) R^T.  Each step of
+ * Algorithm 1 is transposed (the convolution uses the conjugate multiplier), so the
+ * chain mirrors Algorithm 1 in reverse order.  d_sino [batch][n_theta][n_s] ->
+ * d_img [batch][n][n]. */
+rl_status radon_adj(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch,
+                    void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* R^T g, the plain matrix transpose of radon_fwd: (w_X / w_S) * radon_adj.  This is the
+ * gradient map of radon_fwd (for a loss L(R f), dL/df = R^T dL/dg), used by the autograd
+ * wrapper.  Same arguments, workspace (RL_OP_ADJ) and semantics as radon_adj. */
+rl_status radon_transpose(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch,
+                          void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Filtered back-projection f = R# W g (sec. 1 eq. FBP): W is the ramp filter |sigma| of
+ * sec. 6 eq. (ramp), applied along s as a linear (zero-padded) convolution with the
+ * Ram-Lak kernel h_0 = 1/(4 ds^2), h_n = -1/(pi^2 n^2 ds^2) for odd n, 0 for even n != 0
+ * (times ds), then radon_adj.  d_sino [batch][n_theta][n_s] -> d_img [batch][n][n]. */
+rl_status fbp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch,
+              rl_filter filter, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* rl_last_error(void);
+
+/* Intermediate stages of radon_fwd for one slice, exported for stage-by-stage parity
+ * checks.  stage selects what is written to d_out (float32, device):
+ *   RL_STAGE_PREFILTER  c = Q f                                   [n][n]
+ *   RL_STAGE_LOGPOLAR   w = e^rho * decimated fine samples         [m][n_own+4][n_rho]
+ *   RL_STAGE_CONV       periodic convolution on the owned rows    [m][n_own][n_rho]
+ *   RL_STAGE_KERNEL     the multiplier H (complex, interleaved re/im, scaled by
+ *                       1/(k_theta n_rho)), independent of d_img  [n_rho/2+1][k_theta/2+1][2]
+ * Rows of partitions with fewer owned rows than n_own are zero.  d_out_bytes must hold
+ * the stage; the workspace is that of RL_OP_FWD with batch 1. */
+typedef enum {
+  RL_STAGE_PREFILTER = 0,
+  RL_STAGE_LOGPOLAR = 1,
+  RL_STAGE_CONV = 2,
+  RL_STAGE_KERNEL = 3
+} rl_stage;
+
+rl_status rl_debug_stage(const rl_plan* plan, rl_stage stage, const float* d_img, float* d_out,
+                         size_t d_out_bytes, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADONLP_H */

@@ -1,0 +1,115 @@
+"""ctypes loader for libradonlp.so: argument marshalling only.
+
+Every declaration mirrors include/radonlp.h.  Loading the library touches no device.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libradonlp.so")
+
+RL_OK = 0
+STATUS_NAMES = {
+    0: "RL_OK",
+    1: "RL_ERR_INVALID_ARG",
+    2: "RL_ERR_GEOMETRY",
+    3: "RL_ERR_WORKSPACE",
+    4: "RL_ERR_HIP",
+    5: "RL_ERR_UNSUPPORTED_ARCH",
+    6: "RL_ERR_INTERNAL",
+}
+RL_OP_FWD, RL_OP_ADJ, RL_OP_FBP = 0, 1, 2
+RL_FILTER_RAMLAK = 0
+RL_STAGE_PREFILTER, RL_STAGE_LOGPOLAR, RL_STAGE_CONV, RL_STAGE_KERNEL = 0, 1, 2, 3
+
+# Every function declared in include/radonlp.h.
+EXPORTED = (
+    "rl_geom_default",
+    "rl_plan_create",
+    "rl_plan_destroy",
+    "rl_plan_geometry",
+    "rl_workspace_bytes",
+    "radon_fwd",
+    "radon_adj",
+    "radon_transpose",
+    "fbp",
+    "rl_last_error",
+    "rl_debug_stage",
+)
+
+
+class RlGeom(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("n_theta", ctypes.c_int32),
+        ("n_s", ctypes.c_int32),
+        ("m", ctypes.c_int32),
+        ("n_rho", ctypes.c_int32),
+        ("k_theta", ctypes.c_int32),
+        ("r_dec", ctypes.c_int32),
+        ("dec_filter", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class RadonLibError(RuntimeError):
+    def __init__(self, func, status, message):
+        super().__init__(f"{func} failed with {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libradonlp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: the HIP library has not been built "
+            "(run `python -m paper_1506_00014_amd.build`)"
+        )
+    lib = ctypes.CDLL(path)
+    c_int32, c_size_t, c_void_p = ctypes.c_int32, ctypes.c_size_t, ctypes.c_void_p
+    lib.rl_geom_default.argtypes = [c_int32, c_int32, c_int32, c_int32, ctypes.POINTER(RlGeom)]
+    lib.rl_geom_default.restype = c_int32
+    lib.rl_plan_create.argtypes = [ctypes.POINTER(RlGeom), ctypes.POINTER(c_void_p)]
+    lib.rl_plan_create.restype = c_int32
+    lib.rl_plan_destroy.argtypes = [c_void_p]
+    lib.rl_plan_destroy.restype = None
+    lib.rl_plan_geometry.argtypes = [c_void_p, ctypes.POINTER(RlGeom)]
+    lib.rl_plan_geometry.restype = c_int32
+    lib.rl_workspace_bytes.argtypes = [c_void_p, c_int32, c_int32]
+    lib.rl_workspace_bytes.restype = c_size_t
+    for name in ("radon_fwd", "radon_adj", "radon_transpose"):
+        f = getattr(lib, name)
+        f.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]
+        f.restype = c_int32
+    lib.fbp.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_size_t, c_void_p]
+    lib.fbp.restype = c_int32
+    lib.rl_last_error.argtypes = []
+    lib.rl_last_error.restype = ctypes.c_char_p
+    lib.rl_debug_stage.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]
+    lib.rl_debug_stage.restype = c_int32
+    _lib = lib
+    return lib
+
+
+def check(func: str, status: int):
+    if status != RL_OK:
+        msg = _lib.rl_last_error().decode() if _lib is not None else ""
+        raise RadonLibError(func, status, msg)
+
+
+def geom_default(n, n_theta, n_s, m=4) -> RlGeom:
+    lib = load()
+    g = RlGeom()
+    check("rl_geom_default", lib.rl_geom_default(n, n_theta, n_s, m, ctypes.byref(g)))
+    return g

@@ -1,0 +1,182 @@
+"""PyTorch binding of the C-ABI: plans, the three operators, and autograd.
+
+Only argument marshalling happens here: tensors are checked, a workspace is taken from
+torch's caching allocator, and the C entry points are called on the current HIP stream.
+Every step of R, R# and FBP runs in the library's HIP kernels.  There is no fallback:
+without the built library, or without a gfx950 device, the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib
+
+
+def _stream_ptr(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class RadonPlan:
+    """A geometry and its device tables (sec. 3 of the paper: grids, kernel coefficients).
+
+    n, n_theta, n_s: image side, number of angles on [0, pi), detector bins on [-1, 1].
+    m: angular partitions (beta = pi/m); n_rho, k_theta, r_dec: FFT lengths and fine
+    angular oversampling (default: the smallest values meeting the paper's bounds).
+    """
+
+    def __init__(self, n, n_theta, n_s, m=4, n_rho=None, k_theta=None, r_dec=None, device=None):
+        lib = _lib.load()
+        g = _lib.geom_default(n, n_theta, n_s, m)
+        if n_rho is not None:
+            g.n_rho = n_rho
+        if k_theta is not None:
+            g.k_theta = k_theta
+        if r_dec is not None:
+            g.r_dec = r_dec
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self._ptr = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check("rl_plan_create", lib.rl_plan_create(ctypes.byref(g), ctypes.byref(self._ptr)))
+        self.geom = g.as_dict()
+        self._lib = lib
+
+    def __del__(self):
+        ptr = getattr(self, "_ptr", None)
+        if ptr is not None and ptr.value:
+            self._lib.rl_plan_destroy(ptr)
+            self._ptr = None
+
+    # ------------------------------------------------------------------ helpers
+    @property
+    def w_S(self):
+        return (math.pi / self.geom["n_theta"]) * (2.0 / self.geom["n_s"])
+
+    @property
+    def w_X(self):
+        return (2.0 / self.geom["n"]) ** 2
+
+    def workspace_bytes(self, batch, op):
+        return int(self._lib.rl_workspace_bytes(self._ptr, batch, op))
+
+    def _check_in(self, x, shape_tail, name):
+        if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if x.dtype != torch.float32:
+            raise TypeError(f"{name} must be float32")
+        if tuple(x.shape[-2:]) != shape_tail:
+            raise ValueError(f"{name} must end in {shape_tail}, got {tuple(x.shape)}")
+        if x.device != self.device:
+            raise ValueError(f"{name} is on {x.device}, the plan on {self.device}")
+        return x.contiguous()
+
+    def _run(self, fname, x, out_tail, op, ws=None, extra=()):
+        lead = x.shape[:-2]
+        batch = int(math.prod(lead)) if lead else 1
+        out = torch.empty(*lead, *out_tail, dtype=torch.float32, device=x.device)
+        if batch == 0:
+            return out
+        need = self.workspace_bytes(batch, op)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+        f = getattr(self._lib, fname)
+        with torch.cuda.device(self.device):
+            st = f(self._ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), batch, *extra,
+                   ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), _stream_ptr(self.device))
+        _lib.check(fname, st)
+        return out
+
+    # ------------------------------------------------------------------ operators
+    def forward(self, img, ws=None):
+        """R f: [..., n, n] -> [..., n_theta, n_s]."""
+        g = self.geom
+        img = self._check_in(img, (g["n"], g["n"]), "img")
+        return self._run("radon_fwd", img, (g["n_theta"], g["n_s"]), _lib.RL_OP_FWD, ws)
+
+    def adjoint(self, sino, ws=None):
+        """R# g (exact weighted transpose): [..., n_theta, n_s] -> [..., n, n]."""
+        g = self.geom
+        sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
+        return self._run("radon_adj", sino, (g["n"], g["n"]), _lib.RL_OP_ADJ, ws)
+
+    def transpose(self, sino, ws=None):
+        """R^T g = (w_X / w_S) R# g: [..., n_theta, n_s] -> [..., n, n]."""
+        g = self.geom
+        sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
+        return self._run("radon_transpose", sino, (g["n"], g["n"]), _lib.RL_OP_ADJ, ws)
+
+    def fbp(self, sino, ws=None):
+        """R# W g with the Ram-Lak filter: [..., n_theta, n_s] -> [..., n, n]."""
+        g = self.geom
+        sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
+        return self._run("fbp", sino, (g["n"], g["n"]), _lib.RL_OP_FBP, ws, extra=(_lib.RL_FILTER_RAMLAK,))
+
+    def debug_stage(self, stage, img):
+        """Intermediate of the forward chain for one slice (see rl_debug_stage)."""
+        g = self.geom
+        img = self._check_in(img, (g["n"], g["n"]), "img")
+        n_own = None
+        if stage == _lib.RL_STAGE_PREFILTER:
+            shape = (g["n"], g["n"])
+        elif stage == _lib.RL_STAGE_KERNEL:
+            shape = (g["n_rho"] // 2 + 1, g["k_theta"] // 2 + 1, 2)
+        else:
+            n_own = self.n_own()
+            rows = n_own + 4 if stage == _lib.RL_STAGE_LOGPOLAR else n_own
+            shape = (g["m"], rows, g["n_rho"])
+        out = torch.empty(*shape, dtype=torch.float32, device=img.device)
+        need = self.workspace_bytes(1, _lib.RL_OP_FWD)
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=img.device)
+        with torch.cuda.device(self.device):
+            st = self._lib.rl_debug_stage(self._ptr, stage, ctypes.c_void_p(img.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_size_t(out.numel() * 4),
+                                          ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                          _stream_ptr(self.device))
+        _lib.check("rl_debug_stage", st)
+        return out
+
+    def n_own(self):
+        g = self.geom
+        counts = [0] * g["m"]
+        for j in range(g["n_theta"]):
+            mm = (2 * j * g["m"] + g["n_theta"]) // (2 * g["n_theta"])
+            counts[0 if mm == g["m"] else mm] += 1
+        return max(counts)
+
+
+# ---------------------------------------------------------------------- functional API
+def radon_fwd(plan: RadonPlan, img, ws=None):
+    return plan.forward(img, ws)
+
+
+def radon_adj(plan: RadonPlan, sino, ws=None):
+    return plan.adjoint(sino, ws)
+
+
+def radon_transpose(plan: RadonPlan, sino, ws=None):
+    return plan.transpose(sino, ws)
+
+
+def fbp(plan: RadonPlan, sino, ws=None):
+    return plan.fbp(sino, ws)
+
+
+class RadonFn(torch.autograd.Function):
+    """g = R f with the hand-written backward dL/df = R^T dL/dg (the radon_transpose kernels)."""
+
+    @staticmethod
+    def forward(ctx, img, plan):
+        ctx.plan = plan
+        return plan.forward(img)
+
+    @staticmethod
+    def backward(ctx, grad):
+        return ctx.plan.transpose(grad.contiguous()), None
+
+
+def radon(img, plan):
+    """Differentiable R f."""
+    return RadonFn.apply(img, plan)

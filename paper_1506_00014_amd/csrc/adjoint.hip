@@ -1,0 +1,380 @@
+// Back-projection R# as the exact weighted transpose of Algorithm 1, and FBP.
+//
+//   k_splat_rfft   transpose of the polar evaluation (Alg. 1 step 7): each log-polar rho
+//                  node gathers the sinogram samples whose 4-tap B-spline footprint covers
+//                  it (same taps and weights as the forward), times 1/a_R; then a real FFT
+//                  along rho
+//   k_theta_conv   (shared with the forward) with the conjugate multiplier
+//   k_irfft_scale  inverse real FFT along rho of every support row, times e^rho (step 5)
+//   k_lp2cart_adj  transpose of steps 3-4: per 32x32 image tile, every fine log-polar
+//                  sample whose bicubic footprint meets the tile is rebuilt from the coarse
+//                  rows by the decimation filter and spread into LDS with the same 16
+//                  weights the forward gathers with; partitions are summed in the tile
+//   k_prefilter    (shared) Q is symmetric, times w_S / w_X
+//   k_ramp         Ram-Lak filter along s (sec. 6, eq. ramp) as a zero-padded real FFT
+#include <hip/hip_runtime.h>
+
+#include "fft_device.h"
+#include "rl_internal.h"
+
+namespace rl {
+
+__device__ __forceinline__ float bspline_w1(int a, float al) {
+  const float a2 = al * al, a3 = a2 * al, b = 1.0f - al;
+  float w = b * b * b;
+  w = (a == 1) ? (3.0f * a3 - 6.0f * a2 + 4.0f) : w;
+  w = (a == 2) ? (-3.0f * a3 + 3.0f * a2 + 3.0f * al + 1.0f) : w;
+  w = (a == 3) ? a3 : w;
+  return w * (1.0f / 6.0f);
+}
+
+// ------------------------------------------------------------------ transpose of step 7
+__global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float* __restrict__ sino,
+                                                         float2* __restrict__ spec) {
+  extern __shared__ float2 sh[];
+  const int nc = P.nc, nr = P.n_rho, ns = P.n_s;
+  float* xs = reinterpret_cast<float*>(sh);
+  float* gs = reinterpret_cast<float*>(sh + nc);
+  int* kqs = reinterpret_cast<int*>(gs + ns);
+  float* als = reinterpret_cast<float*>(kqs + ns);
+  const int o = blockIdx.x;
+  const int bm = blockIdx.y;
+  const int b = bm / P.m, m = bm - b * P.m;
+  const int jw = P.own_j[m * P.n_own + o];
+  float2* dst = spec + ((size_t)bm * P.n_own + o) * P.ld;
+  if (jw < 0) {  // uniform across the block
+    for (int k = threadIdx.x; k <= nc; k += blockDim.x) dst[k] = make_float2(0.f, 0.f);
+    return;
+  }
+  const int j = jw & ((1 << 30) - 1);
+  const bool wrap = (jw >> 30) & 1;
+  const double cth = P.own_cos[m * P.n_own + o];
+  const double aR = P.a_R;
+  const float* src = sino + ((size_t)b * P.n_theta + j) * ns;
+  for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+    gs[k] = src[k];
+    double s = -1.0 + k * P.ds;
+    if (wrap) s = -s;
+    const double tau = (log(aR * s + (1.0 - aR) * cth) - P.rho0) / P.d_rho;
+    const double ft = floor(tau);
+    kqs[k] = min(max((int)ft, -1), nr);
+    als[k] = (float)(tau - ft);
+  }
+  __syncthreads();
+  const float inv_aR = (float)(1.0 / aR);
+  const double base = (1.0 - aR) * cth;
+  for (int q = threadIdx.x; q < nr; q += blockDim.x) {
+    float acc = 0.f;
+#pragma unroll
+    for (int sh3 = -1; sh3 <= 1; ++sh3) {
+      const int qu = q + sh3 * nr;
+      if (qu < -2 || qu > nr + 1) continue;
+      // sinogram samples with tau in (qu - 2, qu + 2)
+      const double slo = (exp(P.rho0 + (qu - 2) * P.d_rho) - base) / aR;
+      const double shi = (exp(P.rho0 + (qu + 2) * P.d_rho) - base) / aR;
+      double ka, kb;
+      if (!wrap) {
+        ka = (slo + 1.0) / P.ds;
+        kb = (shi + 1.0) / P.ds;
+      } else {
+        ka = (1.0 - shi) / P.ds;
+        kb = (1.0 - slo) / P.ds;
+      }
+      // clamp in double before converting (NaN or huge bounds give an empty or full range)
+      const int k0 = (int)fmin(fmax(floor(ka) - 1.0, 0.0), (double)ns);
+      const int k1 = (int)fmax(fmin(ceil(kb) + 1.0, (double)(ns - 1)), -1.0);
+      for (int k = k0; k <= k1; ++k) {
+        const int a = qu - (kqs[k] - 1);
+        if (a >= 0 && a <= 3) acc += bspline_w1(a, als[k]) * gs[k];
+      }
+    }
+    xs[q] = acc * inv_aR;
+  }
+  __syncthreads();
+  fft_lds<kRowVals, false>(sh, nc, 1, P.tw, P.tw_len);
+  rfft_post(sh, nc, P.tw, P.tw_len, [&](int k, float2 x) { dst[k] = x; });
+}
+
+rl_status launch_splat_rfft(const rl_plan* p, const float* sino, float2* spec, int batch, hipStream_t s) {
+  const DevPlan& d = p->d;
+  const size_t lds = d.nc * sizeof(float2) + (size_t)d.n_s * 3 * sizeof(float);
+  dim3 grid(d.n_own, batch * d.m);
+  if (lds > 65536) {
+    rl_status st = check_hip(hipFuncSetAttribute((const void*)k_splat_rfft, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds),
+                             "hipFuncSetAttribute(k_splat_rfft)");
+    if (st != RL_OK) return st;
+  }
+  hipLaunchKernelGGL(k_splat_rfft, grid, dim3(kThreads), lds, s, d, sino, spec);
+  return check_launch("k_splat_rfft");
+}
+
+// ------------------------------------------------------------------ inverse rho FFT, times e^rho
+__global__ __launch_bounds__(kThreads) void k_irfft_scale(DevPlan P, const float2* __restrict__ spec,
+                                                          float* __restrict__ u) {
+  extern __shared__ float2 sh[];
+  const int nc = P.nc;
+  const size_t row = blockIdx.x;
+  const float2* src = spec + row * P.ld;
+  irfft_pre(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
+  __syncthreads();
+  fft_lds<kRowVals, true>(sh, nc, 1, P.tw, P.tw_len);
+  const float* x = reinterpret_cast<const float*>(sh);
+  float* dst = u + row * P.n_rho;
+  for (int q = threadIdx.x; q < P.n_rho; q += blockDim.x) {
+    const float er = (float)exp((double)(q - P.n_rho + 1) * P.d_rho);
+    dst[q] = x[q] * er;
+  }
+}
+
+rl_status launch_irfft_scale(const rl_plan* p, const float2* spec, float* u, int batch, hipStream_t s) {
+  const DevPlan& d = p->d;
+  hipLaunchKernelGGL(k_irfft_scale, dim3(batch * d.m * d.n_sup), dim3(kThreads), d.nc * sizeof(float2), s, d, spec,
+                     u);
+  return check_launch("k_irfft_scale");
+}
+
+// ------------------------------------------------------------------ transpose of steps 3-4
+__device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+__global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float* __restrict__ U,
+                                                          float* __restrict__ cbar) {
+  __shared__ float acc[kTile][kTile + 1];
+  const int n = P.n, r = P.r;
+  const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
+  const int b = blockIdx.z;
+  for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) acc[i / kTile][i % kTile] = 0.f;
+  __syncthreads();
+  const int txe = min(tx0 + kTile, n), tye = min(ty0 + kTile, n);
+  for (int m = 0; m < P.m; ++m) {
+    const double cb = cos(m * P.beta), sb = sin(m * P.beta);
+    const double2* cs = P.fine_cs + (size_t)m * P.n_fine;
+    const int2* fq = P.fine_q + (size_t)m * P.n_fine;
+    const float* Ub = U + (size_t)(b * P.m + m) * P.n_sup * P.n_rho;
+    // T_m^{-1}(0) in image coordinates
+    const double xs1 = -(1.0 - P.a_R) / P.a_R * cb, xs2 = -(1.0 - P.a_R) / P.a_R * sb;
+    for (int sy = -1; sy <= 1; ++sy) {
+      for (int sx = -1; sx <= 1; ++sx) {
+        const int ux0 = tx0 + sx * n, ux1 = txe + sx * n;
+        const int uy0 = ty0 + sy * n, uy1 = tye + sy * n;
+        // samples whose taps reach the tile have X in [ux0 - 2, ux1 + 1); inside D, X in (0, n)
+        const int Xa = max(ux0 - 2, 0), Xb = min(ux1 + 1, n);
+        const int Ya = max(uy0 - 2, 0), Yb = min(uy1 + 1, n);
+        if (Xa >= Xb || Ya >= Yb) continue;  // uniform across the block
+        const double x1a = -1.0 + Xa * P.dx, x1b = -1.0 + Xb * P.dx;
+        const double x2a = -1.0 + Ya * P.dx, x2b = -1.0 + Yb * P.dx;
+        {
+          const double ex = fmax(fmax(x1a, -x1b), 0.0), ey = fmax(fmax(x2a, -x2b), 0.0);
+          if (ex * ex + ey * ey >= 1.0) continue;  // rectangle misses the unit disc
+        }
+        // polar extent of y = T_m x over the rectangle
+        double phmin = 1e30, phmax = -1e30, emax = 0.0;
+        for (int cidx = 0; cidx < 4; ++cidx) {
+          const double x1 = (cidx & 1) ? x1b : x1a, x2 = (cidx & 2) ? x2b : x2a;
+          const double y1 = P.a_R * (cb * x1 + sb * x2) + (1.0 - P.a_R);
+          const double y2 = P.a_R * (-sb * x1 + cb * x2);
+          const double ph = atan2(y2, y1);
+          phmin = fmin(phmin, ph);
+          phmax = fmax(phmax, ph);
+          emax = fmax(emax, sqrt(y1 * y1 + y2 * y2));
+        }
+        const double ddx = fmax(fmax(x1a - xs1, xs1 - x1b), 0.0), ddy = fmax(fmax(x2a - xs2, xs2 - x2b), 0.0);
+        const double emin = fmax(P.a_R * sqrt(ddx * ddx + ddy * ddy), 1e-300);
+        const double fstep = P.dtheta / r;
+        const int ta = max(P.t_min, (int)floor((phmin - P.phi0[m]) / fstep) - 1);
+        const int tb = min(P.t_min + P.n_fine - 1, (int)ceil((phmax - P.phi0[m]) / fstep) + 1);
+        const int qa = max(0, (int)floor(log(emin) / P.d_rho + P.n_rho - 1) - 1);
+        const int qb = min(P.n_rho - 1, (int)ceil(log(emax) / P.d_rho + P.n_rho - 1) + 1);
+        if (ta > tb || qa > qb) continue;
+        const int nq = qb - qa + 1;
+        const int total = (tb - ta + 1) * nq;
+        for (int cnd = threadIdx.x; cnd < total; cnd += blockDim.x) {
+          const int t = ta + cnd / nq;
+          const int q = qa + cnd % nq;
+          const int ti = t - P.t_min;
+          const int2 qr = fq[ti];
+          if (q < qr.x || q > qr.y) continue;
+          const double2 tcs = cs[ti];
+          const double E = exp((double)(q - P.n_rho + 1) * P.d_rho) / (P.a_R * P.dx);
+          const double X = P.X0[m] + E * tcs.x, Y = P.Y0[m] + E * tcs.y;
+          const double fx = floor(X), fy = floor(Y);
+          const int kx = min(max((int)fx, -1), n), ky = min(max((int)fy, -1), n);
+          if (kx + 2 < ux0 || kx - 1 >= ux1 || ky + 2 < uy0 || ky - 1 >= uy1) continue;
+          // V(t, q): the decimation filter's transpose applied to the coarse rows
+          const int cg = floordiv(t, r);
+          const float4 dw = P.dec[t - r * cg];
+          float V = 0.f;
+          const float wv[4] = {dw.x, dw.y, dw.z, dw.w};
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int row = cg - 1 + a;
+            if (row >= 0 && row < P.n_sup) V += wv[a] * Ub[(size_t)row * P.n_rho + q];
+          }
+          float wx[4], wy[4];
+          bspline_w((float)(X - fx), wx);
+          bspline_w((float)(Y - fy), wy);
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb) {
+            const int ly = ky - 1 + bb - uy0;
+            if (ly < 0 || ly >= uy1 - uy0) continue;
+            const float vy = V * wy[bb];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const int lx = kx - 1 + a - ux0;
+              if (lx >= 0 && lx < ux1 - ux0) atomicAdd(&acc[ly][lx], vy * wx[a]);
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  float* dst = cbar + (size_t)b * n * n;
+  for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
+    const int ly = i / kTile, lx = i % kTile;
+    if (ty0 + ly < n && tx0 + lx < n) dst[(size_t)(ty0 + ly) * n + tx0 + lx] = acc[ly][lx];
+  }
+}
+
+rl_status launch_lp2cart_adj(const rl_plan* p, const float* U, float* cbar, int batch, hipStream_t s) {
+  const DevPlan& d = p->d;
+  dim3 grid((d.n + kTile - 1) / kTile, (d.n + kTile - 1) / kTile, batch);
+  hipLaunchKernelGGL(k_lp2cart_adj, grid, dim3(kThreads), 0, s, d, U, cbar);
+  return check_launch("k_lp2cart_adj");
+}
+
+// ------------------------------------------------------------------ ramp filter
+// One sinogram row per block: zero-pad to lr, real FFT, multiply by the real ramp
+// multiplier, inverse real FFT, keep the first n_s samples.  The multiplier is applied
+// pairwise (k, lr/2 - k) in place between the two packings.
+__global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __restrict__ in, float* __restrict__ out) {
+  extern __shared__ float2 sh[];
+  const int ncr = P.lr / 2, ns = P.n_s;
+  const size_t row = blockIdx.x;
+  float* xs = reinterpret_cast<float*>(sh);
+  const float* src = in + row * ns;
+  for (int i = threadIdx.x; i < P.lr; i += blockDim.x) xs[i] = i < ns ? src[i] : 0.f;
+  __syncthreads();
+  fft_lds<kRowVals, false>(sh, ncr, 1, P.tw, P.tw_len);
+  const int step = P.tw_len / P.lr;
+  for (int k = threadIdx.x; k <= ncr / 2; k += blockDim.x) {
+    const int km = ncr - k;
+    const float2 a = sh[k];
+    const float2 bz = sh[k == 0 ? 0 : km];
+    // forward packing -> X[k], X[km]
+    auto post = [&](float2 za, float2 zb, int kk) {
+      const float2 e = cscale(cadd(za, cconj(zb)), 0.5f);
+      const float2 o = cscale(csub(za, cconj(zb)), 0.5f);
+      const float2 w = P.tw[kk * step];
+      const float2 t = cmul(w, o);
+      return make_float2(e.x + t.y, e.y - t.x);
+    };
+    float2 Xk = post(a, bz, k);
+    float2 Xm = post(bz, a, km);
+    Xk = cscale(Xk, P.ramp[k]);
+    Xm = cscale(Xm, P.ramp[km]);
+    // inverse packing from (Y[k], Y[km])
+    auto pre = [&](float2 ya, float2 yb, int kk) {
+      const float2 bb = cconj(yb);
+      const float2 e = cadd(ya, bb), dd = csub(ya, bb);
+      float2 w = P.tw[kk * step];
+      w.y = -w.y;
+      const float2 oo = cmul(dd, w);
+      return make_float2(e.x - oo.y, e.y + oo.x);
+    };
+    const float2 Zk = pre(Xk, Xm, k);
+    if (k == 0) {
+      sh[0] = Zk;
+    } else {
+      const float2 Zm = pre(Xm, Xk, km);
+      sh[k] = Zk;
+      sh[km] = Zm;
+    }
+  }
+  __syncthreads();
+  fft_lds<kRowVals, true>(sh, ncr, 1, P.tw, P.tw_len);
+  float* dst = out + row * ns;
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) dst[i] = xs[i];
+}
+
+rl_status launch_ramp(const rl_plan* p, const float* in, float* out, int batch, hipStream_t s) {
+  const DevPlan& d = p->d;
+  hipLaunchKernelGGL(k_ramp, dim3(batch * d.n_theta), dim3(kThreads), (size_t)(d.lr / 2) * sizeof(float2), s, d, in,
+                     out);
+  return check_launch("k_ramp");
+}
+
+}  // namespace rl
+
+using namespace rl;
+
+namespace {
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int batch, void* ws, size_t ws_bytes,
+                     rl_op op) {
+  if (!plan) return fail(RL_ERR_INVALID_ARG, "plan is NULL");
+  if (batch < 0) return fail(RL_ERR_INVALID_ARG, "batch is negative");
+  if (batch == 0) return RL_OK;
+  if (!in || !out) return fail(RL_ERR_INVALID_ARG, "input or output pointer is NULL");
+  const size_t ib = (size_t)batch * plan->d.n_theta * plan->d.n_s * sizeof(float);
+  const size_t ob = (size_t)batch * plan->d.n * plan->d.n * sizeof(float);
+  if (overlaps(in, ib, out, ob)) return fail(RL_ERR_INVALID_ARG, "input and output overlap");
+  const size_t need = rl_workspace_bytes(plan, batch, op);
+  if (!ws || ws_bytes < need)
+    return fail(RL_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(need));
+  if (((uintptr_t)ws) & 255) return fail(RL_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (overlaps(ws, need, in, ib) || overlaps(ws, need, out, ob))
+    return fail(RL_ERR_INVALID_ARG, "workspace overlaps input or output");
+  return check_plan_device(plan);
+}
+
+rl_status adjoint_chain(const rl_plan* plan, const float* sino, float* img, int batch, void* ws, rl_op op,
+                        bool transpose, hipStream_t s) {
+  const DevPlan& d = plan->d;
+  const WsLayout L = workspace_layout(plan, batch, op);
+  char* w = (char*)ws;
+  float* cbar = (float*)(w + L.off[0]);
+  float* U = (float*)(w + L.off[1]);
+  float2* Bs = (float2*)(w + L.off[2]);
+  float2* A = (float2*)(w + L.off[3]);
+  rl_status st;
+  if ((st = launch_splat_rfft(plan, sino, A, batch, s)) != RL_OK) return st;
+  if ((st = launch_theta_conv(plan, A, d.n_own, kHalo, Bs, d.n_sup, 0, true, batch, s)) != RL_OK) return st;
+  if ((st = launch_irfft_scale(plan, Bs, U, batch, s)) != RL_OK) return st;
+  if ((st = launch_lp2cart_adj(plan, U, cbar, batch, s)) != RL_OK) return st;
+  const double scale = transpose ? 1.0 : (d.dtheta * d.ds) / (d.dx * d.dx);  // w_S / w_X for R#
+  return launch_prefilter(plan, cbar, img, batch, (float)scale, s);
+}
+
+}  // namespace
+
+extern "C" rl_status radon_adj(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, void* d_ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_ADJ);
+  if (st != RL_OK || batch == 0) return st;
+  return adjoint_chain(plan, d_sino, d_img, batch, d_ws, RL_OP_ADJ, false, stream);
+}
+
+extern "C" rl_status radon_transpose(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch,
+                                     void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_ADJ);
+  if (st != RL_OK || batch == 0) return st;
+  return adjoint_chain(plan, d_sino, d_img, batch, d_ws, RL_OP_ADJ, true, stream);
+}
+
+extern "C" rl_status fbp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, rl_filter filter,
+                         void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  if (filter != RL_FILTER_RAMLAK) return fail(RL_ERR_INVALID_ARG, "only RL_FILTER_RAMLAK is implemented");
+  rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_FBP);
+  if (st != RL_OK || batch == 0) return st;
+  const WsLayout L = workspace_layout(plan, batch, RL_OP_FBP);
+  float* wg = (float*)((char*)d_ws + L.off[4]);
+  if ((st = launch_ramp(plan, d_sino, wg, batch, stream)) != RL_OK) return st;
+  return adjoint_chain(plan, wg, d_img, batch, d_ws, RL_OP_FBP, false, stream);
+}

@@ -1,0 +1,198 @@
+// Device-side building blocks: complex arithmetic, small DFTs, an in-LDS Stockham FFT
+// (self-sorting, radix 8/4/2 passes), real-FFT packing, and cubic B-spline weights.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rl {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward, INV=false) or +i (inverse, INV=true)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2* v) {
+  float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2* v) {
+  float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  float2 t2 = cadd(v[1], v[3]), t3 = mul_mi<INV>(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* v) {
+  const float h = 0.70710678118654752440f;
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<INV>(e);
+  dft4<INV>(o);
+  // twiddles exp(-+ 2 pi i k / 8), k = 0..3
+  float2 o1 = INV ? make_float2(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
+                  : make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+  float2 o2 = mul_mi<INV>(o[2]);
+  float2 o3 = INV ? make_float2(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
+                  : make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 4) dft4<INV>(v);
+  else dft8<INV>(v);
+}
+
+// One Stockham pass of radix R over nfft independent FFTs of length N stored back to back
+// in LDS (buf[f*N + i]).  Ns is the length of the sub-transforms already done.  Every thread
+// of the block must call it (it contains barriers).  MAXB bounds the butterflies per thread.
+template <int R, int MAXB, bool INV>
+__device__ __forceinline__ void stockham_pass(float2* buf, int N, int nfft, int Ns,
+                                              const float2* __restrict__ tw, int tw_len) {
+  const int nbf = N / R;
+  const int total = nbf * nfft;
+  const int step = tw_len / (R * Ns);
+  float2 v[MAXB][R];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int id = threadIdx.x + b * blockDim.x;
+    if (id < total) {
+      const int f = id / nbf;
+      const int j = id - f * nbf;
+      const int k = j & (Ns - 1);
+      const float2* base = buf + f * N;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float2 x = base[j + r * nbf];
+        if (r > 0) {
+          float2 w = tw[r * k * step];
+          if (INV) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        v[b][r] = x;
+      }
+      dft<R, INV>(v[b]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int id = threadIdx.x + b * blockDim.x;
+    if (id < total) {
+      const int f = id / nbf;
+      const int j = id - f * nbf;
+      const int k = j & (Ns - 1);
+      float2* base = buf + f * N;
+      const int o = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) base[o + r * Ns] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Unnormalised in-place FFT (forward: exp(-2 pi i jk/N); INV: exp(+...)) of nfft
+// transforms of power-of-two length N >= 2 held in LDS.  MAXV bounds the complex values
+// per thread: nfft * N <= MAXV * blockDim.x.  Callers synchronise before the call.
+template <int MAXV, bool INV>
+__device__ __forceinline__ void fft_lds(float2* buf, int N, int nfft, const float2* __restrict__ tw,
+                                        int tw_len) {
+  int Ns = 1;
+  while (Ns < N) {
+    const int left = N / Ns;
+    if (left >= 8) {
+      stockham_pass<8, MAXV / 8, INV>(buf, N, nfft, Ns, tw, tw_len);
+      Ns *= 8;
+    } else if (left == 4) {
+      stockham_pass<4, MAXV / 4, INV>(buf, N, nfft, Ns, tw, tw_len);
+      Ns *= 4;
+    } else {
+      stockham_pass<2, MAXV / 2, INV>(buf, N, nfft, Ns, tw, tw_len);
+      Ns *= 2;
+    }
+  }
+}
+
+// Real FFT post-processing: Z = FFT_nc(x[2n] + i x[2n+1]) in LDS -> X[k], k = 0..nc, of the
+// length-2nc real signal.  Calls fn(k, X[k]) for every k in [0, nc].  Threads stride over
+// k in [0, nc/2]; each handles k and nc - k.
+template <class Fn>
+__device__ __forceinline__ void rfft_post(const float2* Z, int nc, const float2* __restrict__ tw,
+                                          int tw_len, Fn fn) {
+  const int step = tw_len / (2 * nc);
+  for (int k = threadIdx.x; k <= nc / 2; k += blockDim.x) {
+    const int km = nc - k;
+    float2 a = Z[k == 0 ? 0 : k];
+    float2 b = Z[k == 0 ? 0 : km];
+    // X[k] = (a + conj b)/2 - i/2 w^k (a - conj b),  w = exp(-2 pi i / (2 nc))
+    float2 e = cscale(cadd(a, cconj(b)), 0.5f);
+    float2 o = cscale(csub(a, cconj(b)), 0.5f);
+    float2 w = tw[k * step];
+    float2 t = cmul(w, o);
+    fn(k, make_float2(e.x + t.y, e.y - t.x));
+    if (km != k) {
+      // X[nc - k] from the same pair with roles swapped
+      float2 e2 = cscale(cadd(b, cconj(a)), 0.5f);
+      float2 o2 = cscale(csub(b, cconj(a)), 0.5f);
+      float2 w2 = (km == nc) ? make_float2(-1.f, 0.f) : tw[km * step];
+      float2 t2 = cmul(w2, o2);
+      fn(km, make_float2(e2.x + t2.y, e2.y - t2.x));
+    }
+  }
+}
+
+// Inverse real FFT pre-processing: X[k], k = 0..nc (read through get(k)) -> Z[k], k < nc,
+// such that the unnormalised inverse FFT_nc of Z gives z[n] = y[2n] + i y[2n+1] where y is
+// the unnormalised inverse DFT of length 2nc of the Hermitian extension of X.
+template <class Get>
+__device__ __forceinline__ void irfft_pre(float2* Z, int nc, const float2* __restrict__ tw,
+                                          int tw_len, Get get) {
+  const int step = tw_len / (2 * nc);
+  for (int k = threadIdx.x; k < nc; k += blockDim.x) {
+    float2 a = get(k);
+    float2 b = cconj(get(nc - k));
+    float2 e = cadd(a, b);
+    float2 d = csub(a, b);
+    float2 w = tw[k * step];
+    w.y = -w.y;                 // exp(+2 pi i k / (2 nc))
+    float2 o = cmul(d, w);
+    Z[k] = make_float2(e.x - o.y, e.y + o.x);   // e + i o
+  }
+}
+
+// Cubic B-spline weights for taps k-1, k, k+1, k+2 at fractional offset a in [0, 1).
+__device__ __forceinline__ void bspline_w(float a, float* w) {
+  const float a2 = a * a, a3 = a2 * a;
+  const float b = 1.0f - a;
+  w[0] = b * b * b * (1.0f / 6.0f);
+  w[1] = (3.0f * a3 - 6.0f * a2 + 4.0f) * (1.0f / 6.0f);
+  w[2] = (-3.0f * a3 + 3.0f * a2 + 3.0f * a + 1.0f) * (1.0f / 6.0f);
+  w[3] = a3 * (1.0f / 6.0f);
+}
+
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+}  // namespace rl

@@ -1,0 +1,361 @@
+// Forward transform R (Algorithm 1 of the paper) and the kernels it shares with the adjoint.
+//
+//   k_prefilter    c = Q f: separable periodic cubic B-spline prefilter (sec. 4, eq.
+//                  Qfrecursive), as the symmetric FIR sqrt(3) z^|k|, |k| <= 16, z = sqrt(3) - 2
+//   k_cart2lp      Alg. 1 steps 3-5: bicubic samples of T_m f on the fine log-polar grid
+//                  (eq. Tdef, Lopolargrid_f, wsumn), zero outside D (eq. circle_D), theta
+//                  low-pass + decimation to the coarse grid (eq. Lopolargrid_polar), times e^rho
+//   k_rfft_rows    real FFT along rho of every support row
+//   k_theta_conv   FFT along theta, multiply by H = zeta_hat / (B_hat D_hat) (eq. exprcoef1;
+//                  Alg. 1 step 6), inverse FFT along theta, kept rows only
+//   k_irfft_eval   inverse real FFT along rho, then the 4-tap B-spline evaluation at
+//                  S_m(theta_j, s_k) (eq. Sm_def, Radon_all_pb; Alg. 1 step 7), times 1/a_R
+#include <hip/hip_runtime.h>
+
+#include "fft_device.h"
+#include "rl_internal.h"
+
+namespace rl {
+
+// ------------------------------------------------------------------ prefilter
+constexpr int kPT = 32;             // output tile side
+constexpr int kPI = kPT + 2 * kPrefR;  // input tile side
+
+__global__ __launch_bounds__(kThreads) void k_prefilter(const float* __restrict__ in, float* __restrict__ out,
+                                                        int n, float scale, const float* __restrict__ pref) {
+  __shared__ float tin[kPI][kPI + 1];
+  __shared__ float trow[kPI][kPT + 1];
+  __shared__ float q[kPrefR + 1];
+  const int b = blockIdx.z;
+  const int ty0 = blockIdx.y * kPT, tx0 = blockIdx.x * kPT;
+  const float* src = in + (size_t)b * n * n;
+  if (threadIdx.x <= kPrefR) q[threadIdx.x] = pref[threadIdx.x];
+  for (int idx = threadIdx.x; idx < kPI * kPI; idx += blockDim.x) {
+    const int ly = idx / kPI, lx = idx % kPI;
+    int gy = (ty0 - kPrefR + ly) % n;
+    int gx = (tx0 - kPrefR + lx) % n;
+    gy += gy < 0 ? n : 0;
+    gx += gx < 0 ? n : 0;
+    tin[ly][lx] = src[(size_t)gy * n + gx];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kPI * kPT; idx += blockDim.x) {
+    const int ly = idx / kPT, lx = idx % kPT;
+    float acc = q[0] * tin[ly][lx + kPrefR];
+#pragma unroll
+    for (int k = 1; k <= kPrefR; ++k) acc += q[k] * (tin[ly][lx + kPrefR - k] + tin[ly][lx + kPrefR + k]);
+    trow[ly][lx] = acc;
+  }
+  __syncthreads();
+  float* dst = out + (size_t)b * n * n;
+  for (int idx = threadIdx.x; idx < kPT * kPT; idx += blockDim.x) {
+    const int ly = idx / kPT, lx = idx % kPT;
+    float acc = q[0] * trow[ly + kPrefR][lx];
+#pragma unroll
+    for (int k = 1; k <= kPrefR; ++k) acc += q[k] * (trow[ly + kPrefR - k][lx] + trow[ly + kPrefR + k][lx]);
+    const int gy = ty0 + ly, gx = tx0 + lx;
+    if (gy < n && gx < n) dst[(size_t)gy * n + gx] = acc * scale;
+  }
+}
+
+rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int batch, float scale, hipStream_t s) {
+  const int n = p->d.n;
+  dim3 grid((n + kPT - 1) / kPT, (n + kPT - 1) / kPT, batch);
+  hipLaunchKernelGGL(k_prefilter, grid, dim3(kThreads), 0, s, in, out, n, scale, p->d.pref);
+  return check_launch("k_prefilter");
+}
+
+// ------------------------------------------------------------------ cart -> log-polar
+constexpr int kSegRows = 16;  // coarse rows produced by one block
+
+// One thread per rho index q; the block walks the fine rows of kSegRows coarse rows (plus the
+// filter reach) in order, keeping the four coarse rows a fine row feeds in registers.
+__global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __restrict__ c, float* __restrict__ u) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.n_rho) return;
+  const int bm = blockIdx.z;
+  const int b = bm / P.m, m = bm - b * P.m;
+  const int i0 = blockIdx.y * kSegRows;
+  const int i1 = min(i0 + kSegRows, P.n_sup);
+  const int n = P.n, r = P.r;
+  const double rho = (double)(q - P.n_rho + 1) * P.d_rho;
+  const double er = exp(rho);
+  const double E = er / (P.a_R * P.dx);
+  const float erf_ = (float)er;
+  const double X0 = P.X0[m], Y0 = P.Y0[m];
+  const float* img = c + (size_t)b * n * n;
+  const double2* cs = P.fine_cs + (size_t)m * P.n_fine;
+  const int2* fq = P.fine_q + (size_t)m * P.n_fine;
+  float* urow = u + ((size_t)bm * P.n_sup) * P.n_rho + q;
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+  for (int cg = i0 - 2; cg <= i1; ++cg) {
+    for (int ph = 0; ph < r; ++ph) {
+      const int ti = r * cg + ph - P.t_min;
+      float v = 0.f;
+      if (ti >= 0 && ti < P.n_fine) {
+        const int2 qr = fq[ti];
+        if (q >= qr.x && q <= qr.y) {
+          const double2 t = cs[ti];
+          const double X = X0 + E * t.x, Y = Y0 + E * t.y;
+          const double fx = floor(X), fy = floor(Y);
+          float wx[4], wy[4];
+          bspline_w((float)(X - fx), wx);
+          bspline_w((float)(Y - fy), wy);
+          const int kx = min(max((int)fx, -1), n), ky = min(max((int)fy, -1), n);
+          int cx[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) cx[a] = wrap1(kx - 1 + a, n);
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb) {
+            const float* row = img + (size_t)wrap1(ky - 1 + bb, n) * n;
+            const float h = wx[0] * row[cx[0]] + wx[1] * row[cx[1]] + wx[2] * row[cx[2]] + wx[3] * row[cx[3]];
+            v += wy[bb] * h;
+          }
+        }
+      }
+      const float4 dw = P.dec[ph];
+      acc0 += dw.x * v;
+      acc1 += dw.y * v;
+      acc2 += dw.z * v;
+      acc3 += dw.w * v;
+    }
+    const int row = cg - 1;
+    if (row >= i0 && row < i1) urow[(size_t)row * P.n_rho] = acc0 * erf_;
+    acc0 = acc1;
+    acc1 = acc2;
+    acc2 = acc3;
+    acc3 = 0.f;
+  }
+}
+
+rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s) {
+  const DevPlan& d = p->d;
+  dim3 grid((d.n_rho + kThreads - 1) / kThreads, (d.n_sup + kSegRows - 1) / kSegRows, batch * d.m);
+  hipLaunchKernelGGL(k_cart2lp, grid, dim3(kThreads), 0, s, d, c, u);
+  return check_launch("k_cart2lp");
+}
+
+// ------------------------------------------------------------------ rho FFTs of rows
+// in: real rows of length n_rho (stride n_rho); out: half spectra X[0..nc] (stride ld).
+__global__ __launch_bounds__(kThreads) void k_rfft_rows(DevPlan P, const float* __restrict__ in,
+                                                        float2* __restrict__ out) {
+  extern __shared__ float2 sh[];
+  const int nc = P.nc;
+  const size_t row = blockIdx.x;
+  const float2* src = reinterpret_cast<const float2*>(in + row * P.n_rho);
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) sh[i] = src[i];
+  __syncthreads();
+  fft_lds<kRowVals, false>(sh, nc, 1, P.tw, P.tw_len);
+  float2* dst = out + row * P.ld;
+  rfft_post(sh, nc, P.tw, P.tw_len, [&](int k, float2 x) { dst[k] = x; });
+}
+
+rl_status launch_rfft_rows(const rl_plan* p, const float* in, float2* out, int rows, hipStream_t s) {
+  const DevPlan& d = p->d;
+  hipLaunchKernelGGL(k_rfft_rows, dim3(rows), dim3(kThreads), d.nc * sizeof(float2), s, d, in, out);
+  return check_launch("k_rfft_rows");
+}
+
+// Inverse of k_rfft_rows without normalisation: out rows of length n_rho.
+__global__ __launch_bounds__(kThreads) void k_irfft_rows(DevPlan P, const float2* __restrict__ in,
+                                                         float* __restrict__ out) {
+  extern __shared__ float2 sh[];
+  const int nc = P.nc;
+  const size_t row = blockIdx.x;
+  const float2* src = in + row * P.ld;
+  irfft_pre(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
+  __syncthreads();
+  fft_lds<kRowVals, true>(sh, nc, 1, P.tw, P.tw_len);
+  float2* dst = reinterpret_cast<float2*>(out + row * P.n_rho);
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) dst[i] = sh[i];
+}
+
+rl_status launch_irfft_rows(const rl_plan* p, const float2* in, float* out, int rows, hipStream_t s) {
+  const DevPlan& d = p->d;
+  hipLaunchKernelGGL(k_irfft_rows, dim3(rows), dim3(kThreads), d.nc * sizeof(float2), s, d, in, out);
+  return check_launch("k_irfft_rows");
+}
+
+// ------------------------------------------------------------------ theta convolution
+// Block: CW spectrum columns of one (slice, partition).  LDS holds the CW columns as
+// contiguous length-K vectors; rows outside the input range are zero.
+__global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2* __restrict__ in, int in_rows,
+                                                         int in_off, float2* __restrict__ out, int out_rows,
+                                                         int out_off, int conj, int cw) {
+  extern __shared__ float2 sh[];
+  const int K = P.k_theta, nkt = K / 2 + 1, ncol = P.nc + 1;
+  const int bm = blockIdx.y;
+  const int col0 = blockIdx.x * cw;
+  const float2* src = in + (size_t)bm * in_rows * P.ld;
+  for (int idx = threadIdx.x; idx < cw * K; idx += blockDim.x) {
+    const int cl = idx % cw, row = idx / cw;
+    const int col = col0 + cl;
+    const int ir = row - in_off;
+    float2 v = make_float2(0.f, 0.f);
+    if (col < ncol && ir >= 0 && ir < in_rows) v = src[(size_t)ir * P.ld + col];
+    sh[cl * K + row] = v;
+  }
+  __syncthreads();
+  fft_lds<kColVals, false>(sh, K, cw, P.tw, P.tw_len);
+  for (int idx = threadIdx.x; idx < cw * K; idx += blockDim.x) {
+    const int cl = idx / K, kt = idx % K;
+    const int col = col0 + cl;
+    if (col < ncol) {
+      const int akt = kt <= K / 2 ? kt : K - kt;
+      float2 h = P.H[(size_t)col * nkt + akt];
+      if (conj) h.y = -h.y;
+      sh[idx] = cmul(sh[idx], h);
+    }
+  }
+  __syncthreads();
+  fft_lds<kColVals, true>(sh, K, cw, P.tw, P.tw_len);
+  float2* dst = out + (size_t)bm * out_rows * P.ld;
+  for (int idx = threadIdx.x; idx < cw * out_rows; idx += blockDim.x) {
+    const int cl = idx % cw, orow = idx / cw;
+    const int col = col0 + cl;
+    if (col < ncol) dst[(size_t)orow * P.ld + col] = sh[cl * K + orow + out_off];
+  }
+}
+
+rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out, int out_rows,
+                            int out_off, bool conj, int batch, hipStream_t s) {
+  const DevPlan& d = p->d;
+  const int cw = (kColVals * kThreads) / d.k_theta >= 8 ? 8 : (kColVals * kThreads) / d.k_theta;
+  dim3 grid((d.nc + 1 + cw - 1) / cw, batch * d.m);
+  hipLaunchKernelGGL(k_theta_conv, grid, dim3(kThreads), (size_t)cw * d.k_theta * sizeof(float2), s, d, in,
+                     in_rows, in_off, out, out_rows, out_off, conj ? 1 : 0, cw);
+  return check_launch("k_theta_conv");
+}
+
+// ------------------------------------------------------------------ inverse rho FFT + evaluation
+// Block: one owned row of one (slice, partition); writes sinogram row j.
+__global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2* __restrict__ spec,
+                                                         float* __restrict__ sino) {
+  extern __shared__ float2 sh[];
+  const int o = blockIdx.x;
+  const int bm = blockIdx.y;
+  const int b = bm / P.m, m = bm - b * P.m;
+  const int jw = P.own_j[m * P.n_own + o];
+  if (jw < 0) return;  // uniform across the block
+  const int j = jw & ((1 << 30) - 1);
+  const bool wrap = (jw >> 30) & 1;
+  const int nc = P.nc, nr = P.n_rho;
+  const float2* src = spec + ((size_t)bm * P.n_own + o) * P.ld;
+  irfft_pre(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
+  __syncthreads();
+  fft_lds<kRowVals, true>(sh, nc, 1, P.tw, P.tw_len);
+  const float* x = reinterpret_cast<const float*>(sh);
+  const double cth = P.own_cos[m * P.n_own + o];
+  const double aR = P.a_R;
+  const float inv_aR = (float)(1.0 / aR);
+  float* dst = sino + ((size_t)b * P.n_theta + j) * P.n_s;
+  for (int k = threadIdx.x; k < P.n_s; k += blockDim.x) {
+    double s = -1.0 + k * P.ds;
+    if (wrap) s = -s;
+    const double tau = (log(aR * s + (1.0 - aR) * cth) - P.rho0) / P.d_rho;
+    const double ft = floor(tau);
+    float w[4];
+    bspline_w((float)(tau - ft), w);
+    const int kq = min(max((int)ft, -1), nr);
+    float acc = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc += w[a] * x[wrap1(kq - 1 + a, nr)];
+    dst[k] = acc * inv_aR;
+  }
+}
+
+rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, float* sino, int batch, hipStream_t s) {
+  const DevPlan& d = p->d;
+  dim3 grid(d.n_own, batch * d.m);
+  hipLaunchKernelGGL(k_irfft_eval, grid, dim3(kThreads), d.nc * sizeof(float2), s, d, spec, sino);
+  return check_launch("k_irfft_eval");
+}
+
+}  // namespace rl
+
+using namespace rl;
+
+namespace {
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+rl_status common_checks(const rl_plan* plan, const void* in, const void* out, int batch, void* ws, size_t ws_bytes,
+                        rl_op op, size_t in_bytes, size_t out_bytes) {
+  if (!plan) return fail(RL_ERR_INVALID_ARG, "plan is NULL");
+  if (batch < 0) return fail(RL_ERR_INVALID_ARG, "batch is negative");
+  if (batch == 0) return RL_OK;
+  if (!in || !out) return fail(RL_ERR_INVALID_ARG, "input or output pointer is NULL");
+  if (overlaps(in, in_bytes, out, out_bytes)) return fail(RL_ERR_INVALID_ARG, "input and output overlap");
+  const size_t need = rl_workspace_bytes(plan, batch, op);
+  if (!ws || ws_bytes < need)
+    return fail(RL_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(need));
+  if (((uintptr_t)ws) & 255) return fail(RL_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (overlaps(ws, need, in, in_bytes) || overlaps(ws, need, out, out_bytes))
+    return fail(RL_ERR_INVALID_ARG, "workspace overlaps input or output");
+  return check_plan_device(plan);
+}
+
+rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int batch, void* ws, int stop_stage,
+                        float* stage_out, hipStream_t s) {
+  const DevPlan& d = plan->d;
+  const WsLayout L = workspace_layout(plan, batch, RL_OP_FWD);
+  char* w = (char*)ws;
+  float* c = (float*)(w + L.off[0]);
+  float* u = (float*)(w + L.off[1]);
+  float2* A = (float2*)(w + L.off[2]);
+  float2* Bs = (float2*)(w + L.off[3]);
+  rl_status st;
+  if ((st = launch_prefilter(plan, img, stop_stage == RL_STAGE_PREFILTER ? stage_out : c, batch, 1.0f, s)) != RL_OK)
+    return st;
+  if (stop_stage == RL_STAGE_PREFILTER) return RL_OK;
+  if ((st = launch_cart2lp(plan, c, stop_stage == RL_STAGE_LOGPOLAR ? stage_out : u, batch, s)) != RL_OK) return st;
+  if (stop_stage == RL_STAGE_LOGPOLAR) return RL_OK;
+  if ((st = launch_rfft_rows(plan, u, A, batch * d.m * d.n_sup, s)) != RL_OK) return st;
+  if ((st = launch_theta_conv(plan, A, d.n_sup, 0, Bs, d.n_own, kHalo, false, batch, s)) != RL_OK) return st;
+  if (stop_stage == RL_STAGE_CONV) return launch_irfft_rows(plan, Bs, stage_out, batch * d.m * d.n_own, s);
+  return launch_irfft_eval(plan, Bs, sino, batch, s);
+}
+
+}  // namespace
+
+extern "C" rl_status radon_fwd(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch, void* d_ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  rl_status st = RL_OK;
+  if (plan) {
+    const size_t ib = (size_t)batch * plan->d.n * plan->d.n * sizeof(float);
+    const size_t ob = (size_t)batch * plan->d.n_theta * plan->d.n_s * sizeof(float);
+    st = common_checks(plan, d_img, d_sino, batch, d_ws, ws_bytes, RL_OP_FWD, ib, ob);
+  } else {
+    st = fail(RL_ERR_INVALID_ARG, "plan is NULL");
+  }
+  if (st != RL_OK || batch == 0) return st;
+  return forward_chain(plan, d_img, d_sino, batch, d_ws, -1, nullptr, stream);
+}
+
+extern "C" rl_status rl_debug_stage(const rl_plan* plan, rl_stage stage, const float* d_img, float* d_out,
+                                    size_t d_out_bytes, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  if (!plan || !d_out) return fail(RL_ERR_INVALID_ARG, "NULL argument");
+  const DevPlan& d = plan->d;
+  size_t need = 0;
+  switch (stage) {
+    case RL_STAGE_PREFILTER: need = (size_t)d.n * d.n * sizeof(float); break;
+    case RL_STAGE_LOGPOLAR: need = (size_t)d.m * d.n_sup * d.n_rho * sizeof(float); break;
+    case RL_STAGE_CONV: need = (size_t)d.m * d.n_own * d.n_rho * sizeof(float); break;
+    case RL_STAGE_KERNEL: need = (size_t)(d.nc + 1) * (d.k_theta / 2 + 1) * sizeof(float2); break;
+    default: return fail(RL_ERR_INVALID_ARG, "unknown stage");
+  }
+  if (d_out_bytes < need) return fail(RL_ERR_INVALID_ARG, "d_out too small for the stage");
+  rl_status st = check_plan_device(plan);
+  if (st != RL_OK) return st;
+  if (stage == RL_STAGE_KERNEL)
+    return check_hip(hipMemcpyAsync(d_out, d.H, need, hipMemcpyDeviceToDevice, stream), "copy kernel table");
+  if (!d_img) return fail(RL_ERR_INVALID_ARG, "d_img is NULL");
+  const size_t ib = (size_t)d.n * d.n * sizeof(float);
+  st = common_checks(plan, d_img, d_out, 1, d_ws, ws_bytes, RL_OP_FWD, ib, need);
+  if (st != RL_OK) return st;
+  return forward_chain(plan, d_img, nullptr, 1, d_ws, (int)stage, d_out, stream);
+}

@@ -1,0 +1,86 @@
+// Internal declarations of the log-polar Radon library (gfx950).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "radonlp.h"
+
+namespace rl {
+
+constexpr int kHalo = 2;          // coarse rows on each side of a partition's owned rows
+constexpr int kThreads = 256;     // threads per block of every hot-path kernel
+constexpr int kRowVals = 16;      // complex values per thread in a row FFT (N_rho/2 <= 4096)
+constexpr int kColVals = 32;      // complex values per thread in the theta pass
+constexpr int kTile = 32;         // image tile side of the adjoint splat
+constexpr int kPrefR = 16;        // half-length of the truncated prefilter (|z|^17 ~ 2e-10)
+constexpr int kMaxPart = 16;      // largest supported M
+
+// Scalars and device tables handed to every kernel by value.
+struct DevPlan {
+  int n, n_theta, n_s, m, n_rho, k_theta, r;
+  int n_own, n_sup, n_fine, t_min, ld, nc, tw_len, lr;
+  double a_R, dx, ds, dtheta, d_rho, rho0, beta;
+  double X0[kMaxPart], Y0[kMaxPart];   // image index of T_m^{-1}(0) offsets, per partition
+  double phi0[kMaxPart];               // theta' of support row 0, per partition
+  const float2* H;         // [nc + 1][k_theta/2 + 1], zeta_hat/(B_hat D_hat K N_rho)
+  const double2* fine_cs;  // [m][n_fine] (cos(phi_t + m beta), sin(phi_t + m beta))
+  const int2* fine_q;      // [m][n_fine] inclusive rho-index range inside D (lo > hi: empty)
+  const float4* dec;       // [r] weights of the decimation filter for phase p
+  const int* own_j;        // [m][n_own] sinogram row, bit 30 set for wrapped rows, -1 if none
+  const double* own_cos;   // [m][n_own] cos(theta'_j)
+  const float2* tw;        // [tw_len] exp(-2 pi i n / tw_len)
+  const float* ramp;       // [lr/2 + 1] ramp multiplier (real), includes 1/lr
+  const float* pref;       // [kPrefR + 1] prefilter taps sqrt(3) z^|k|
+};
+
+}  // namespace rl
+
+struct rl_plan {
+  rl_geom g;
+  int device;
+  rl::DevPlan d;
+  std::vector<int> rows_per_part;
+  void* d_mem;  // single device allocation holding all tables
+  size_t d_mem_bytes;
+};
+
+namespace rl {
+
+// ---------------------------------------------------------------- error handling
+void set_error(const std::string& msg);
+rl_status fail(rl_status code, const std::string& msg);
+rl_status check_hip(hipError_t e, const char* what);
+rl_status check_launch(const char* what);
+rl_status check_plan_device(const rl_plan* plan);
+
+struct WsLayout {
+  size_t off[6];
+  size_t total;
+};
+WsLayout workspace_layout(const rl_plan* plan, int batch, rl_op op);
+
+// Launchers (forward.hip / adjoint.hip).
+rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int batch, float scale,
+                           hipStream_t s);
+rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s);
+rl_status launch_rfft_rows(const rl_plan* p, const float* in, float2* out, int rows, hipStream_t s);
+rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out,
+                            int out_rows, int out_off, bool conj, int batch, hipStream_t s);
+rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, float* sino, int batch,
+                            hipStream_t s);
+rl_status launch_splat_rfft(const rl_plan* p, const float* sino, float2* spec, int batch,
+                            hipStream_t s);
+rl_status launch_irfft_scale(const rl_plan* p, const float2* spec, float* u, int batch,
+                             hipStream_t s);
+rl_status launch_lp2cart_adj(const rl_plan* p, const float* u, float* cbar, int batch,
+                             hipStream_t s);
+rl_status launch_ramp(const rl_plan* p, const float* in, float* out, int batch, hipStream_t s);
+rl_status launch_irfft_rows(const rl_plan* p, const float2* spec, float* out, int rows,
+                            hipStream_t s);
+
+}  // namespace rl

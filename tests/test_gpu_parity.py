@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle on the same seeded
+inputs.  Bar: relative L2 <= 1e-5 for R, R#, FBP and R^T; the error against FP64 is printed
+for every case.  Stage tests compare the intermediates rl_debug_stage exports."""
+
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import kernel as okernel  # noqa: E402
+from oracle import radon as oradon  # noqa: E402
+from oracle import bspline as obspline  # noqa: E402
+from oracle.geometry import Geometry  # noqa: E402
+from paper_1506_00014_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    a = a.astype(np.complex128) if np.iscomplexobj(a) else a.astype(np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+_plans = {}
+
+
+def get_plan(n, nt, ns, m=4, **kw):
+    from paper_1506_00014_amd import RadonPlan
+
+    key = (n, nt, ns, m, tuple(sorted(kw.items())))
+    if key not in _plans:
+        p = RadonPlan(n, nt, ns, m=m, **kw)
+        g = p.geom
+        og = Geometry(g["n"], g["n_theta"], g["n_s"], g["m"], g["n_rho"], g["k_theta"], g["r_dec"]).validate()
+        _plans[key] = (p, og)
+    return _plans[key]
+
+
+def to_dev(x, dev):
+    return torch.tensor(np.asarray(x, np.float32), device=dev)
+
+
+def f32(x):
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+CASES = [
+    # (n, n_theta, n_s, m, extra): small sizes spanning several tiles and ragged tails
+    (128, 180, 128, 4, {}),   # the 128 x 128, 180-angle configuration
+    (64, 90, 64, 4, {}),
+    (48, 100, 40, 3, {}),     # M = 3, M does not divide N_theta
+    (96, 97, 80, 5, {}),      # odd N_theta, N_s != N, ragged tiles
+    (32, 48, 32, 4, {"n_rho": 128, "r_dec": 8}),  # oversampled geometry
+    (16, 24, 16, 4, {}),      # smaller than one tile
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
+def test_forward_parity(dev, case):
+    n, nt, ns, m, kw = case
+    plan, og = get_plan(n, nt, ns, m, **kw)
+    img, _ = inputs.ellipse_phantom(n, 8, 101)
+    img += 0.3 * inputs.uniform_image(n, 103)  # nonzero up to the image border
+    got = plan.forward(to_dev(img, dev)).cpu().numpy()
+    ref = oradon.radon_fwd(og, f32(img))
+    e = rel(got, ref)
+    print(f"R {case}: rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
+def test_adjoint_parity(dev, case):
+    n, nt, ns, m, kw = case
+    plan, og = get_plan(n, nt, ns, m, **kw)
+    g = inputs.normal_array((nt, ns), 102)
+    got = plan.adjoint(to_dev(g, dev)).cpu().numpy()
+    ref = oradon.radon_adj(og, f32(g))
+    e = rel(got, ref)
+    print(f"R# {case}: rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
+    gt = plan.transpose(to_dev(g, dev)).cpu().numpy()
+    et = rel(gt, ref * (og.w_X / og.w_S))
+    print(f"R^T {case}: rel L2 {et:.2e}")
+    assert et <= TOL
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
+def test_fbp_parity(dev, case):
+    n, nt, ns, m, kw = case
+    plan, og = get_plan(n, nt, ns, m, **kw)
+    img, ells = inputs.ellipse_phantom(n, 8, 101)
+    from oracle import analytic
+
+    g = analytic.ellipse_sino(og.theta_nodes(), og.s_nodes(), ells)
+    got = plan.fbp(to_dev(g, dev)).cpu().numpy()
+    ref = oradon.fbp(og, f32(g))
+    e = rel(got, ref)
+    print(f"FBP {case}: rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
+
+
+def test_stage_parity(dev):
+    from paper_1506_00014_amd import _lib
+
+    n, nt, ns = 128, 180, 128
+    plan, og = get_plan(n, nt, ns)
+    img = inputs.uniform_image(n, 104) - 0.5
+    x = to_dev(img, dev)
+    # prefilter
+    c_gpu = plan.debug_stage(_lib.RL_STAGE_PREFILTER, x).cpu().numpy()
+    c_ref = obspline.prefilter_2d(f32(img))
+    assert rel(c_gpu, c_ref) <= 1e-6
+    # kernel table (scaled by 1 / (K N_rho)), stored [k_rho][k_theta]
+    Hg = plan.debug_stage(_lib.RL_STAGE_KERNEL, x).cpu().numpy()
+    Hg = Hg[..., 0] + 1j * Hg[..., 1]
+    Hr = okernel.multiplier_half(og).T / (og.k_theta * og.n_rho)
+    assert rel(Hg, Hr) <= 1e-6
+    # log-polar samples w (rows of each partition's support) and the convolution output
+    w_gpu = plan.debug_stage(_lib.RL_STAGE_LOGPOLAR, x).cpu().numpy()
+    conv_gpu = plan.debug_stage(_lib.RL_STAGE_CONV, x).cpu().numpy()
+    c64 = obspline.prefilter_2d(f32(img))
+    for p in range(og.m):
+        clp = oradon._partition_forward(og, c64, p, "fft")
+        # the oracle's step S5 output is recomputed here from its pieces
+        n_sup_p = len(og.partition_rows(p)) + 4
+        ti, q, X, Y = oradon.fine_sample_points(og, p)
+        t = og.fine_rows(p)
+        v = np.zeros((t.size, og.n_rho))
+        v[ti, q] = obspline.eval_periodic_2d(c64, X, Y)
+        d = okernel.decimation_taps(og.r_dec)
+        r = og.r_dec
+        u = np.stack([d @ v[r * i - (2 * r - 1) - t[0]: r * i - (2 * r - 1) - t[0] + 4 * r - 1]
+                      for i in range(n_sup_p)])
+        w = u * np.exp(og.rho_nodes())[None, :]
+        assert rel(w_gpu[p, :n_sup_p], w) <= 1e-6, p
+        own = len(og.partition_rows(p))
+        assert rel(conv_gpu[p, :own], clp[2:2 + own]) <= 2e-6, p
+
+
+def test_batch_equals_single_slices(dev):
+    n, nt, ns = 64, 90, 64
+    plan, og = get_plan(n, nt, ns)
+    imgs = np.stack([inputs.ellipse_phantom(n, 5, 200 + i)[0] for i in range(3)])
+    x = to_dev(imgs, dev)
+    batched = plan.forward(x).cpu().numpy()
+    for i in range(3):
+        single = plan.forward(x[i]).cpu().numpy()
+        assert np.array_equal(batched[i], single)
+    g = inputs.normal_array((3, nt, ns), 5)
+    gb = plan.adjoint(to_dev(g, dev)).cpu().numpy()
+    for i in range(3):
+        gs = plan.adjoint(to_dev(g[i], dev)).cpu().numpy()
+        assert np.max(np.abs(gb[i] - gs)) <= 1e-6 * np.abs(gs).max()
+    assert plan.forward(torch.empty(0, n, n, device=dev)).shape == (0, nt, ns)
+
+
+def test_adjoint_identity_fp32(dev):
+    n, nt, ns = 128, 180, 128
+    plan, og = get_plan(n, nt, ns)
+    f = inputs.normal_array((n, n), 21)
+    g = inputs.normal_array((nt, ns), 22)
+    Rf = plan.forward(to_dev(f, dev)).double().cpu().numpy()
+    Rsg = plan.adjoint(to_dev(g, dev)).double().cpu().numpy()
+    lhs = og.w_S * np.sum(Rf * g)
+    rhs = og.w_X * np.sum(f * Rsg)
+    scale = og.w_S * np.linalg.norm(Rf) * np.linalg.norm(g)
+    print(f"adjoint identity FP32: {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+def test_autograd_gradient_matches_oracle(dev):
+    from paper_1506_00014_amd import RadonFn
+
+    n, nt, ns = 128, 180, 128
+    plan, og = get_plan(n, nt, ns)
+    img, _ = inputs.ellipse_phantom(n, 8, 331)
+    g = oradon.radon_fwd(og, img) + 0.01 * inputs.normal_array((nt, ns), 332)
+    f0 = inputs.uniform_image(n, 333)
+    f = to_dev(f0, dev).requires_grad_(True)
+    y = to_dev(g, dev)
+    loss = ((RadonFn.apply(f, plan) - y) ** 2).sum()
+    loss.backward()
+    grad = f.grad.double().cpu().numpy()
+    ref = 2.0 * (og.w_X / og.w_S) * oradon.radon_adj(og, oradon.radon_fwd(og, f32(f0)) - f32(g))
+    e = rel(grad, ref)
+    print(f"autograd gradient vs oracle 2 R^T (R f - g): {e:.2e}")
+    assert e <= TOL
+
+
+def test_errors_on_device(dev):
+    from paper_1506_00014_amd import _lib
+
+    plan, og = get_plan(64, 90, 64)
+    x = torch.zeros(2, 64, 64, device=dev)
+    y = torch.zeros(2, 90, 64, device=dev)
+    lib = _lib.load()
+    import ctypes
+
+    small = torch.empty(16, dtype=torch.uint8, device=dev)
+    st = lib.radon_fwd(plan._ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), 2,
+                       ctypes.c_void_p(small.data_ptr()), 16, None)
+    assert st == 3  # workspace too small
+    ws = torch.empty(plan.workspace_bytes(2, 0), dtype=torch.uint8, device=dev)
+    st = lib.radon_fwd(plan._ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr() + 4), 2,
+                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
+    assert st == 1  # overlapping input and output
+    st = lib.radon_fwd(plan._ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), 0, None, 0, None)
+    assert st == 0  # batch 0 is a no-op
+    with pytest.raises(Exception):
+        plan.forward(torch.zeros(64, 64, dtype=torch.float64, device=dev))
