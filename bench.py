@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark: slices/s of the log-polar R, R# and FBP on one MI355X.
+
+One step = the whole hot path on one batch of 2048 x 2048 slices (2048 angles x 2048 bins):
+g = R f, then R# g, then FBP g (ramp + R#).  Inputs are resident in HBM before the timed
+region.  Also reported: per-operator slices/s batched (one call for the batch) vs plain
+(batch-1 calls in a loop), per-kernel durations from HIP events recorded on the launch
+stream, the roofline position of the dominant kernel, and the FP64 oracle timed on the
+host on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "slices/s for R and R# at N=2048 fp32, batched vs plain; % of HBM peak"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def kernel_bytes(name, g, n_own, batch):
+    """Algorithmic HBM bytes of one launch of each kernel (what it must read and write)."""
+    n, nt, ns, m, nr, K = g["n"], g["n_theta"], g["n_s"], g["m"], g["n_rho"], g["k_theta"]
+    n_sup = n_own + 4
+    nc1 = nr // 2 + 1
+    img = 4 * n * n
+    sino = 4 * nt * ns
+    lp_sup = 4 * m * n_sup * nr
+    sp_sup = 8 * m * n_sup * nc1
+    sp_own = 8 * m * n_own * nc1
+    table = 8 * nc1 * (K // 2 + 1)
+    per_slice = {
+        "k_prefilter": 2 * img,
+        "k_cart2lp": img + lp_sup,
+        "k_rfft_rows": lp_sup + sp_sup,
+        "k_theta_conv": sp_sup + sp_own,
+        "k_irfft_eval": sp_own + sino,
+        "k_splat_rfft": sino + sp_own,
+        "k_irfft_scale": sp_sup + lp_sup,
+        "k_lp2cart_adj": lp_sup + img,
+        "k_ramp": 2 * sino,
+    }
+    extra = table if name == "k_theta_conv" else 0
+    return per_slice[name] * batch + extra
+
+
+def cpu_baseline(g, seed=303):
+    """The FP64 oracle on one of the M partitions of one slice: R, R# and the FBP filter.
+
+    Per-slice time = prefilters + M x (partition forward + partition transpose) + ramp."""
+    import numpy as np
+
+    from oracle import bspline, radon as oradon
+    from oracle.geometry import Geometry
+    from paper_1506_00014_amd import inputs
+
+    og = Geometry(g["n"], g["n_theta"], g["n_s"], g["m"], g["n_rho"], g["k_theta"], g["r_dec"]).validate()
+    f = inputs.uniform_image(g["n"], seed)
+    t0 = time.perf_counter()
+    oradon._H(og)  # plan-time kernel table, not part of the sample
+    t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    c = bspline.prefilter_2d(f)
+    t_q = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    clp = oradon._partition_forward(og, c, 0, "fft")
+    gpart = np.zeros((og.n_theta, og.n_s))
+    for i, j, tau in oradon.eval_taus(og, 0):
+        gpart[j] = bspline.eval_periodic_1d(clp[i], tau) / og.a_R
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    w = oradon.ramp_filter(og, gpart)
+    t_ramp_part = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cb = oradon._partition_adjoint(og, gpart, 0, "fft")
+    t_adj = time.perf_counter() - t0
+    del w, cb
+    M = og.m
+    t_ramp = t_ramp_part  # ramp_filter runs over every sinogram row
+    # one step per slice: R (Q + M partitions), R# (M partitions + Q), FBP (ramp + M partitions + Q)
+    per_slice = (t_q + M * t_fwd) + (M * t_adj + t_q) + (t_ramp + M * t_adj + t_q)
+    sample = t_q + t_fwd + t_adj + t_ramp_part
+    return {
+        "value": 1.0 / per_slice,
+        "unit": "slices/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"partition 0 of {M} of one {g['n']}x{g['n']} slice ({g['n_theta']}x{g['n_s']} sinogram): "
+                   f"prefilter {t_q:.2f}s, partition forward {t_fwd:.2f}s, partition transpose {t_adj:.2f}s, "
+                   f"ramp on its rows {t_ramp_part:.2f}s; {sample:.1f}s of CPU work scaled to one step per slice "
+                   f"(R + R# + FBP = 3 prefilters + {M} forward + {2 * M} transposed partitions + ramp); "
+                   f"plan-time kernel table {t_plan:.1f}s excluded; numpy FP64, single thread"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); slices are independent, so "
+              "a multi-GPU run would shard the batch with no communication.", file=sys.stderr)
+        sys.exit(2)
+
+    import ctypes
+
+    import torch
+
+    from paper_1506_00014_amd import RadonPlan, _lib
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    n = args.n
+    B = args.batch
+    plan = RadonPlan(n, n, n)
+    g = plan.geom
+    n_own = plan.n_own()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(303)
+    f = torch.rand(B, n, n, generator=gen, device=dev, dtype=torch.float32)
+    ws_bytes = max(plan.workspace_bytes(B, op) for op in (0, 1, 2))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ws1 = torch.empty(max(plan.workspace_bytes(1, op) for op in (0, 1, 2)), dtype=torch.uint8, device=dev)
+    lib = _lib.load()
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    log(f"plan {g}, batch {B}, workspace {ws_bytes / 2**30:.2f} GiB")
+
+    def step():
+        sino = plan.forward(f, ws)
+        back = plan.adjoint(sino, ws)
+        rec = plan.fbp(sino, ws)
+        return sino, back, rec
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+    K = args.steps
+    _lib.check("rl_profile_start", lib.rl_profile_start(32 * K + 64))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.rl_profile_stop()
+    log(f"timed {K} steps")
+    ms_per_step = (t1 - t0) * 1000.0 / K
+    value = B / (ms_per_step / 1000.0)
+
+    # per-kernel durations (HIP events on the launch stream, over the timed region)
+    per_kernel = {}
+    name = ctypes.c_char_p()
+    ms = ctypes.c_float()
+    for i in range(lib.rl_profile_count()):
+        _lib.check("rl_profile_record", lib.rl_profile_record(i, ctypes.byref(name), ctypes.byref(ms)))
+        e = per_kernel.setdefault(name.value.decode(), [0, 0.0])
+        e[0] += 1
+        e[1] += ms.value
+    kernels = {}
+    for kname, (cnt, tot) in per_kernel.items():
+        avg = tot / cnt
+        by = kernel_bytes(kname, g, n_own, B)
+        kernels[kname] = {"launches": cnt, "avg_ms": round(avg, 4), "ms_per_step": round(tot / K, 4),
+                          "alg_bytes_per_launch": by, "alg_GBps": round(by / (avg * 1e-3) / 1e9, 1)}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    dk = kernels[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dk["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": None}
+
+    # per-operator rates, batched vs plain
+    def time_op(fn, reps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    sino = plan.forward(f, ws)
+    torch.cuda.synchronize()
+    reps = max(1, K // 2)
+    ops = {
+        "R": (lambda: plan.forward(f, ws), lambda i: plan.forward(f[i], ws1)),
+        "R#": (lambda: plan.adjoint(sino, ws), lambda i: plan.adjoint(sino[i], ws1)),
+        "FBP": (lambda: plan.fbp(sino, ws), lambda i: plan.fbp(sino[i], ws1)),
+    }
+    detail = {"per_op": {}, "kernels": kernels}
+    for op, (batched, single) in ops.items():
+        tb = time_op(batched, reps)
+        rec = {"batched_slices_per_s": round(B / (tb / 1000.0), 1), "batched_ms_per_slice": round(tb / B, 4)}
+        if not args.no_plain:
+            tp = time_op(lambda: [single(i) for i in range(B)], 1)
+            rec["plain_slices_per_s"] = round(B / (tp / 1000.0), 1)
+            rec["batched_over_plain"] = round(tp / tb, 3)
+        detail["per_op"][op] = rec
+        log(f"{op}: {rec}")
+    detail["paper_context"] = ("GTX 770, CUDA 7, FP32, M=3, N_theta=1.5N: R# 9.9e-2 s per 2048^2 slice "
+                               "(10.1 slices/s); one R + one R# 0.205 s per slice (4.9 slices/s); context only")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "slices/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"R, R# and FBP (ramp) on a batch of {B} slices of {n}x{n}, "
+                               f"{g['n_theta']} angles x {g['n_s']} bins, f ~ U[0,1]",
+                   "n": n, "n_theta": g["n_theta"], "n_s": g["n_s"], "batch": B, "m": g["m"],
+                   "n_rho": g["n_rho"], "k_theta": g["k_theta"], "r_dec": g["r_dec"]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(g)
+    out["detail"] = detail
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -162,6 +162,18 @@ typedef enum {
 rl_status rl_debug_stage(const rl_plan* plan, rl_stage stage, const float* d_img, float* d_out,
                          size_t d_out_bytes, void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* Kernel timing hooks (for benchmarks).  While recording is on, every kernel the library
+ * enqueues is bracketed by a pair of HIP events recorded on the same stream, so the
+ * durations are those of the kernels themselves.  rl_profile_start discards earlier
+ * records and keeps at most `capacity` new ones (event pairs are created here, host side;
+ * no device memory is allocated).  rl_profile_record waits for record i to complete and
+ * returns the kernel name (static storage) and its duration in milliseconds.  Not
+ * thread-safe; meant for single-threaded benchmark drivers. */
+rl_status rl_profile_start(int32_t capacity);
+rl_status rl_profile_stop(void);
+int32_t rl_profile_count(void);
+rl_status rl_profile_record(int32_t i, const char** name, float* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -198,30 +198,35 @@ def radon_fwd(geom, f, mode="fft"):
     return g
 
 
+def _partition_adjoint(geom, g, p, mode):
+    """Partition p's share of R^T g before the prefilter: S3^T S4^T S5^T S6^T S7^T."""
+    r = geom.r_dec
+    d = decimation_taps(r)
+    Nr = geom.n_rho
+    C = np.zeros((geom.k_theta, Nr))
+    for i, j, tau in eval_taus(geom, p):                             # S7^T
+        k, wts = bspline.taps(tau)
+        for a in range(4):
+            C[i] += np.bincount((k - 1 + a) % Nr, weights=wts[a] * g[j], minlength=Nr) / geom.a_R
+    Wt = _conv(geom, C, conj=True, mode=mode)                        # S6^T
+    n_sup_p = len(geom.partition_rows(p)) + 2 * HALO
+    w = Wt[:n_sup_p] * np.exp(geom.rho_nodes())[None, :]            # S5^T
+    t = geom.fine_rows(p)
+    v = np.zeros((t.size, Nr))
+    for i in range(n_sup_p):                                         # S4^T
+        base = r * i - (2 * r - 1) - t[0]
+        v[base:base + 4 * r - 1] += np.outer(d, w[i])
+    ti, q, X, Y = fine_sample_points(geom, p)
+    return _bicubic_transpose(v[ti, q], X, Y, (geom.n, geom.n))      # S3^T
+
+
 def radon_adj(geom, g, mode="fft"):
     """R# g = (w_S / w_X) R^T g: g[N_theta, N_s] -> f[N, N]."""
     g = np.asarray(g, dtype=np.float64)
     assert g.shape == (geom.n_theta, geom.n_s)
-    r = geom.r_dec
-    d = decimation_taps(r)
     cbar = np.zeros((geom.n, geom.n))
     for p in range(geom.m):
-        Nr = geom.n_rho
-        C = np.zeros((geom.k_theta, Nr))
-        for i, j, tau in eval_taus(geom, p):                         # S7^T
-            k, wts = bspline.taps(tau)
-            for a in range(4):
-                C[i] += np.bincount((k - 1 + a) % Nr, weights=wts[a] * g[j], minlength=Nr) / geom.a_R
-        Wt = _conv(geom, C, conj=True, mode=mode)                    # S6^T
-        n_sup_p = len(geom.partition_rows(p)) + 2 * HALO
-        w = Wt[:n_sup_p] * np.exp(geom.rho_nodes())[None, :]        # S5^T
-        t = geom.fine_rows(p)
-        v = np.zeros((t.size, Nr))
-        for i in range(n_sup_p):                                     # S4^T
-            base = r * i - (2 * r - 1) - t[0]
-            v[base:base + 4 * r - 1] += np.outer(d, w[i])
-        ti, q, X, Y = fine_sample_points(geom, p)
-        cbar += _bicubic_transpose(v[ti, q], X, Y, cbar.shape)       # S3^T
+        cbar += _partition_adjoint(geom, g, p, mode)
     return bspline.prefilter_2d(cbar) * (geom.w_S / geom.w_X)        # S2^T = S2
 
 

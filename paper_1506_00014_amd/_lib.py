@@ -38,6 +38,10 @@ EXPORTED = (
     "fbp",
     "rl_last_error",
     "rl_debug_stage",
+    "rl_profile_start",
+    "rl_profile_stop",
+    "rl_profile_count",
+    "rl_profile_record",
 )
 
 
@@ -98,6 +102,14 @@ def load(path: str = LIB_PATH):
     lib.rl_last_error.restype = ctypes.c_char_p
     lib.rl_debug_stage.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]
     lib.rl_debug_stage.restype = c_int32
+    lib.rl_profile_start.argtypes = [c_int32]
+    lib.rl_profile_start.restype = c_int32
+    lib.rl_profile_stop.argtypes = []
+    lib.rl_profile_stop.restype = c_int32
+    lib.rl_profile_count.argtypes = []
+    lib.rl_profile_count.restype = c_int32
+    lib.rl_profile_record.argtypes = [c_int32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float)]
+    lib.rl_profile_record.restype = c_int32
     _lib = lib
     return lib
 

@@ -105,7 +105,7 @@ rl_status launch_splat_rfft(const rl_plan* p, const float* sino, float2* spec, i
                              "hipFuncSetAttribute(k_splat_rfft)");
     if (st != RL_OK) return st;
   }
-  hipLaunchKernelGGL(k_splat_rfft, grid, dim3(kThreads), lds, s, d, sino, spec);
+  RL_LAUNCH("k_splat_rfft", k_splat_rfft, grid, dim3(kThreads), lds, s, d, sino, spec);
   return check_launch("k_splat_rfft");
 }
 
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void k_irfft_scale(DevPlan P, const float
 
 rl_status launch_irfft_scale(const rl_plan* p, const float2* spec, float* u, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
-  hipLaunchKernelGGL(k_irfft_scale, dim3(batch * d.m * d.n_sup), dim3(kThreads), d.nc * sizeof(float2), s, d, spec,
+  RL_LAUNCH("k_irfft_scale", k_irfft_scale, dim3(batch * d.m * d.n_sup), dim3(kThreads), d.nc * sizeof(float2), s, d, spec,
                      u);
   return check_launch("k_irfft_scale");
 }
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
 rl_status launch_lp2cart_adj(const rl_plan* p, const float* U, float* cbar, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   dim3 grid((d.n + kTile - 1) / kTile, (d.n + kTile - 1) / kTile, batch);
-  hipLaunchKernelGGL(k_lp2cart_adj, grid, dim3(kThreads), 0, s, d, U, cbar);
+  RL_LAUNCH("k_lp2cart_adj", k_lp2cart_adj, grid, dim3(kThreads), 0, s, d, U, cbar);
   return check_launch("k_lp2cart_adj");
 }
 
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __res
 
 rl_status launch_ramp(const rl_plan* p, const float* in, float* out, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
-  hipLaunchKernelGGL(k_ramp, dim3(batch * d.n_theta), dim3(kThreads), (size_t)(d.lr / 2) * sizeof(float2), s, d, in,
+  RL_LAUNCH("k_ramp", k_ramp, dim3(batch * d.n_theta), dim3(kThreads), (size_t)(d.lr / 2) * sizeof(float2), s, d, in,
                      out);
   return check_launch("k_ramp");
 }

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kThreads) void k_prefilter(const float* __restrict_
 rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int batch, float scale, hipStream_t s) {
   const int n = p->d.n;
   dim3 grid((n + kPT - 1) / kPT, (n + kPT - 1) / kPT, batch);
-  hipLaunchKernelGGL(k_prefilter, grid, dim3(kThreads), 0, s, in, out, n, scale, p->d.pref);
+  RL_LAUNCH("k_prefilter", k_prefilter, grid, dim3(kThreads), 0, s, in, out, n, scale, p->d.pref);
   return check_launch("k_prefilter");
 }
 
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
 rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   dim3 grid((d.n_rho + kThreads - 1) / kThreads, (d.n_sup + kSegRows - 1) / kSegRows, batch * d.m);
-  hipLaunchKernelGGL(k_cart2lp, grid, dim3(kThreads), 0, s, d, c, u);
+  RL_LAUNCH("k_cart2lp", k_cart2lp, grid, dim3(kThreads), 0, s, d, c, u);
   return check_launch("k_cart2lp");
 }
 
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_rfft_rows(DevPlan P, const float* 
 
 rl_status launch_rfft_rows(const rl_plan* p, const float* in, float2* out, int rows, hipStream_t s) {
   const DevPlan& d = p->d;
-  hipLaunchKernelGGL(k_rfft_rows, dim3(rows), dim3(kThreads), d.nc * sizeof(float2), s, d, in, out);
+  RL_LAUNCH("k_rfft_rows", k_rfft_rows, dim3(rows), dim3(kThreads), d.nc * sizeof(float2), s, d, in, out);
   return check_launch("k_rfft_rows");
 }
 
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_irfft_rows(DevPlan P, const float2
 
 rl_status launch_irfft_rows(const rl_plan* p, const float2* in, float* out, int rows, hipStream_t s) {
   const DevPlan& d = p->d;
-  hipLaunchKernelGGL(k_irfft_rows, dim3(rows), dim3(kThreads), d.nc * sizeof(float2), s, d, in, out);
+  RL_LAUNCH("k_irfft_rows", k_irfft_rows, dim3(rows), dim3(kThreads), d.nc * sizeof(float2), s, d, in, out);
   return check_launch("k_irfft_rows");
 }
 
@@ -222,7 +222,7 @@ rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int
   const DevPlan& d = p->d;
   const int cw = (kColVals * kThreads) / d.k_theta >= 8 ? 8 : (kColVals * kThreads) / d.k_theta;
   dim3 grid((d.nc + 1 + cw - 1) / cw, batch * d.m);
-  hipLaunchKernelGGL(k_theta_conv, grid, dim3(kThreads), (size_t)cw * d.k_theta * sizeof(float2), s, d, in,
+  RL_LAUNCH("k_theta_conv", k_theta_conv, grid, dim3(kThreads), (size_t)cw * d.k_theta * sizeof(float2), s, d, in,
                      in_rows, in_off, out, out_rows, out_off, conj ? 1 : 0, cw);
   return check_launch("k_theta_conv");
 }
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2
 rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, float* sino, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   dim3 grid(d.n_own, batch * d.m);
-  hipLaunchKernelGGL(k_irfft_eval, grid, dim3(kThreads), d.nc * sizeof(float2), s, d, spec, sino);
+  RL_LAUNCH("k_irfft_eval", k_irfft_eval, grid, dim3(kThreads), d.nc * sizeof(float2), s, d, spec, sino);
   return check_launch("k_irfft_eval");
 }
 

@@ -206,6 +206,29 @@ rl_status check_plan_device(const rl_plan* plan) {
   return RL_OK;
 }
 
+// ---------------------------------------------------------------- kernel timing hooks
+namespace {
+struct Profiler {
+  bool on = false;
+  int capacity = 0;
+  int used = 0;
+  std::vector<hipEvent_t> start, stop;
+  std::vector<const char*> names;
+} g_prof;
+}  // namespace
+
+int prof_open(const char* name, hipStream_t s) {
+  if (!g_prof.on || g_prof.used >= g_prof.capacity) return -1;
+  const int slot = g_prof.used++;
+  g_prof.names[slot] = name;
+  (void)hipEventRecord(g_prof.start[slot], s);
+  return slot;
+}
+
+void prof_close(int slot, hipStream_t s) {
+  if (slot >= 0) (void)hipEventRecord(g_prof.stop[slot], s);
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 WsLayout workspace_layout(const rl_plan* plan, int batch, rl_op op) {
@@ -532,3 +555,40 @@ extern "C" size_t rl_workspace_bytes(const rl_plan* plan, int32_t batch, rl_op o
 }
 
 extern "C" const char* rl_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" rl_status rl_profile_start(int32_t capacity) {
+  if (capacity < 0) return fail(RL_ERR_INVALID_ARG, "negative capacity");
+  g_prof.on = false;
+  while ((int)g_prof.start.size() < capacity) {
+    hipEvent_t a, b;
+    rl_status st = check_hip(hipEventCreate(&a), "hipEventCreate");
+    if (st != RL_OK) return st;
+    st = check_hip(hipEventCreate(&b), "hipEventCreate");
+    if (st != RL_OK) {
+      (void)hipEventDestroy(a);
+      return st;
+    }
+    g_prof.start.push_back(a);
+    g_prof.stop.push_back(b);
+  }
+  g_prof.names.assign(g_prof.start.size(), "");
+  g_prof.capacity = capacity;
+  g_prof.used = 0;
+  g_prof.on = true;
+  return RL_OK;
+}
+
+extern "C" rl_status rl_profile_stop(void) {
+  g_prof.on = false;
+  return RL_OK;
+}
+
+extern "C" int32_t rl_profile_count(void) { return g_prof.used; }
+
+extern "C" rl_status rl_profile_record(int32_t i, const char** name, float* ms) {
+  if (i < 0 || i >= g_prof.used || !name || !ms) return fail(RL_ERR_INVALID_ARG, "bad profile record index");
+  rl_status st = check_hip(hipEventSynchronize(g_prof.stop[i]), "hipEventSynchronize");
+  if (st != RL_OK) return st;
+  *name = g_prof.names[i];
+  return check_hip(hipEventElapsedTime(ms, g_prof.start[i], g_prof.stop[i]), "hipEventElapsedTime");
+}

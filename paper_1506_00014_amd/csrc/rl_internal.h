@@ -64,6 +64,18 @@ struct WsLayout {
 };
 WsLayout workspace_layout(const rl_plan* plan, int batch, rl_op op);
 
+// Kernel timing hooks: prof_open records a start event (returns a slot or -1), prof_close
+// the matching stop event, both on the launch stream.
+int prof_open(const char* name, hipStream_t s);
+void prof_close(int slot, hipStream_t s);
+
+#define RL_LAUNCH(name, kernel, grid, block, lds, stream, ...)                      \
+  do {                                                                            \
+    const int rl_slot_ = ::rl::prof_open(name, stream);                           \
+    hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);            \
+    ::rl::prof_close(rl_slot_, stream);                                           \
+  } while (0)
+
 // Launchers (forward.hip / adjoint.hip).
 rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int batch, float scale,
                            hipStream_t s);
