@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void k_irfft_scale(DevPlan P, const float
   const float* x = reinterpret_cast<const float*>(sh);
   float* dst = u + row * P.n_rho;
   for (int q = threadIdx.x; q < P.n_rho; q += blockDim.x) {
-    const float er = (float)exp((double)(q - P.n_rho + 1) * P.d_rho);
+    const float er = (float)(P.erho[q] * (P.a_R * P.dx));
     dst[q] = x[q] * er;
   }
 }
@@ -137,13 +137,49 @@ rl_status launch_irfft_scale(const rl_plan* p, const float2* spec, float* u, int
 // ------------------------------------------------------------------ transpose of steps 3-4
 __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
+// Block: one kTile x kTile image tile.  For every partition, the fine log-polar rays that
+// cross the tile are listed first (one thread per ray): a ray t is the half-line
+// x* + E (cos psi_t, sin psi_t) in image-index coordinates (x* = T_m^{-1}(0),
+// E = e^rho / (a_R dx)); the rho indices whose bicubic footprint can reach the tile are
+// those where the ray crosses the tile grown by two pixels (slab test), intersected with
+// the ray's range inside D.  A block-wide scan then flattens the (ray, rho) samples, and all
+// threads walk them: each sample is rebuilt from the coarse rows by the transposed
+// decimation filter and spread with the 16 bicubic weights into the LDS tile.
+constexpr int kARows = 512;  // rays listed per pass
+
+__device__ __forceinline__ int block_exclusive_scan(int* buf, int nitems) {
+  // in-place exclusive scan of buf[0..nitems), nitems <= 2 * blockDim.x; returns the total
+  __shared__ int part[kThreads];
+  const int t = threadIdx.x;
+  const int a = 2 * t < nitems ? buf[2 * t] : 0;
+  const int b = 2 * t + 1 < nitems ? buf[2 * t + 1] : 0;
+  part[t] = a + b;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  const int incl = part[t];
+  const int excl = incl - (a + b);
+  if (2 * t < nitems) buf[2 * t] = excl;
+  if (2 * t + 1 < nitems) buf[2 * t + 1] = excl + a;
+  const int total = part[blockDim.x - 1];
+  __syncthreads();
+  return total;
+}
+
 __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float* __restrict__ U,
                                                           float* __restrict__ cbar) {
-  __shared__ float acc[kTile][kTile + 1];
+  __shared__ double acc[kTile][kTile + 1];  // FP64: LDS float atomics are slow on this target
+  __shared__ int rq0[kARows];
+  __shared__ int rpre[kARows + 1];
+  __shared__ double2 rcs[kARows];
   const int n = P.n, r = P.r;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
   const int b = blockIdx.z;
-  for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) acc[i / kTile][i % kTile] = 0.f;
+  for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) acc[i / kTile][i % kTile] = 0.0;
   __syncthreads();
   const int txe = min(tx0 + kTile, n), tye = min(ty0 + kTile, n);
   for (int m = 0; m < P.m; ++m) {
@@ -151,8 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
     const double2* cs = P.fine_cs + (size_t)m * P.n_fine;
     const int2* fq = P.fine_q + (size_t)m * P.n_fine;
     const float* Ub = U + (size_t)(b * P.m + m) * P.n_sup * P.n_rho;
-    // T_m^{-1}(0) in image coordinates
-    const double xs1 = -(1.0 - P.a_R) / P.a_R * cb, xs2 = -(1.0 - P.a_R) / P.a_R * sb;
+    const double X0 = P.X0[m], Y0 = P.Y0[m];
     for (int sy = -1; sy <= 1; ++sy) {
       for (int sx = -1; sx <= 1; ++sx) {
         const int ux0 = tx0 + sx * n, ux1 = txe + sx * n;
@@ -161,69 +196,98 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
         const int Xa = max(ux0 - 2, 0), Xb = min(ux1 + 1, n);
         const int Ya = max(uy0 - 2, 0), Yb = min(uy1 + 1, n);
         if (Xa >= Xb || Ya >= Yb) continue;  // uniform across the block
-        const double x1a = -1.0 + Xa * P.dx, x1b = -1.0 + Xb * P.dx;
-        const double x2a = -1.0 + Ya * P.dx, x2b = -1.0 + Yb * P.dx;
         {
+          const double x1a = -1.0 + Xa * P.dx, x1b = -1.0 + Xb * P.dx;
+          const double x2a = -1.0 + Ya * P.dx, x2b = -1.0 + Yb * P.dx;
           const double ex = fmax(fmax(x1a, -x1b), 0.0), ey = fmax(fmax(x2a, -x2b), 0.0);
           if (ex * ex + ey * ey >= 1.0) continue;  // rectangle misses the unit disc
         }
-        // polar extent of y = T_m x over the rectangle
-        double phmin = 1e30, phmax = -1e30, emax = 0.0;
-        for (int cidx = 0; cidx < 4; ++cidx) {
-          const double x1 = (cidx & 1) ? x1b : x1a, x2 = (cidx & 2) ? x2b : x2a;
-          const double y1 = P.a_R * (cb * x1 + sb * x2) + (1.0 - P.a_R);
-          const double y2 = P.a_R * (-sb * x1 + cb * x2);
-          const double ph = atan2(y2, y1);
+        // angular extent of the rectangle seen from x* (which lies outside it)
+        double phmin = 1e30, phmax = -1e30;
+        for (int c = 0; c < 4; ++c) {
+          const double dX = ((c & 1) ? Xb : Xa) - X0, dY = ((c & 2) ? Yb : Ya) - Y0;
+          const double ph = atan2(-sb * dX + cb * dY, cb * dX + sb * dY);
           phmin = fmin(phmin, ph);
           phmax = fmax(phmax, ph);
-          emax = fmax(emax, sqrt(y1 * y1 + y2 * y2));
         }
-        const double ddx = fmax(fmax(x1a - xs1, xs1 - x1b), 0.0), ddy = fmax(fmax(x2a - xs2, xs2 - x2b), 0.0);
-        const double emin = fmax(P.a_R * sqrt(ddx * ddx + ddy * ddy), 1e-300);
         const double fstep = P.dtheta / r;
         const int ta = max(P.t_min, (int)floor((phmin - P.phi0[m]) / fstep) - 1);
         const int tb = min(P.t_min + P.n_fine - 1, (int)ceil((phmax - P.phi0[m]) / fstep) + 1);
-        const int qa = max(0, (int)floor(log(emin) / P.d_rho + P.n_rho - 1) - 1);
-        const int qb = min(P.n_rho - 1, (int)ceil(log(emax) / P.d_rho + P.n_rho - 1) + 1);
-        if (ta > tb || qa > qb) continue;
-        const int nq = qb - qa + 1;
-        const int total = (tb - ta + 1) * nq;
-        for (int cnd = threadIdx.x; cnd < total; cnd += blockDim.x) {
-          const int t = ta + cnd / nq;
-          const int q = qa + cnd % nq;
-          const int ti = t - P.t_min;
-          const int2 qr = fq[ti];
-          if (q < qr.x || q > qr.y) continue;
-          const double2 tcs = cs[ti];
-          const double E = exp((double)(q - P.n_rho + 1) * P.d_rho) / (P.a_R * P.dx);
-          const double X = P.X0[m] + E * tcs.x, Y = P.Y0[m] + E * tcs.y;
-          const double fx = floor(X), fy = floor(Y);
-          const int kx = min(max((int)fx, -1), n), ky = min(max((int)fy, -1), n);
-          if (kx + 2 < ux0 || kx - 1 >= ux1 || ky + 2 < uy0 || ky - 1 >= uy1) continue;
-          // V(t, q): the decimation filter's transpose applied to the coarse rows
-          const int cg = floordiv(t, r);
-          const float4 dw = P.dec[t - r * cg];
-          float V = 0.f;
-          const float wv[4] = {dw.x, dw.y, dw.z, dw.w};
-#pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const int row = cg - 1 + a;
-            if (row >= 0 && row < P.n_sup) V += wv[a] * Ub[(size_t)row * P.n_rho + q];
+        for (int tc = ta; tc <= tb; tc += kARows) {
+          const int nrows = min(kARows, tb - tc + 1);
+          // 1) rho range of each ray inside the grown tile and inside D
+          for (int k = threadIdx.x; k < nrows; k += blockDim.x) {
+            const int ti = tc + k - P.t_min;
+            const int2 qr = fq[ti];
+            const double2 tcs = cs[ti];
+            int cnt = 0, qa = 0;
+            if (qr.x <= qr.y) {
+              double elo = 0.0, ehi = 1e300;
+              bool ok = true;
+              if (fabs(tcs.x) > 1e-15) {
+                const double e1 = (Xa - X0) / tcs.x, e2 = (Xb - X0) / tcs.x;
+                elo = fmax(elo, fmin(e1, e2));
+                ehi = fmin(ehi, fmax(e1, e2));
+              } else {
+                ok = ok && X0 >= Xa && X0 <= Xb;
+              }
+              if (fabs(tcs.y) > 1e-15) {
+                const double e1 = (Ya - Y0) / tcs.y, e2 = (Yb - Y0) / tcs.y;
+                elo = fmax(elo, fmin(e1, e2));
+                ehi = fmin(ehi, fmax(e1, e2));
+              } else {
+                ok = ok && Y0 >= Ya && Y0 <= Yb;
+              }
+              if (ok && elo <= ehi && ehi > 0.0) {
+                const double scale = P.a_R * P.dx;
+                qa = max(qr.x, (int)floor(log(fmax(elo * scale, 1e-300)) / P.d_rho + P.n_rho - 1) - 1);
+                const int qb = min(qr.y, (int)ceil(log(ehi * scale) / P.d_rho + P.n_rho - 1) + 1);
+                cnt = max(0, qb - qa + 1);
+              }
+            }
+            rq0[k] = qa;
+            rpre[k] = cnt;
+            rcs[k] = tcs;
           }
-          float wx[4], wy[4];
-          bspline_w((float)(X - fx), wx);
-          bspline_w((float)(Y - fy), wy);
+          __syncthreads();
+          const int total = block_exclusive_scan(rpre, nrows);
+          if (threadIdx.x == 0) rpre[nrows] = total;
+          __syncthreads();
+          // 2) walk the flattened samples
+          int k = 0;
+          for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+            while (rpre[k + 1] <= idx) ++k;
+            const int t = tc + k;
+            const int q = rq0[k] + (idx - rpre[k]);
+            const double2 tcs = rcs[k];
+            const double E = P.erho[q];
+            const double X = X0 + E * tcs.x, Y = Y0 + E * tcs.y;
+            const double fx = floor(X), fy = floor(Y);
+            const int kx = min(max((int)fx, -1), n), ky = min(max((int)fy, -1), n);
+            if (kx + 2 < ux0 || kx - 1 >= ux1 || ky + 2 < uy0 || ky - 1 >= uy1) continue;
+            const int cg = floordiv(t, r);
+            const float4 dw = P.dec[t - r * cg];
+            float V = 0.f;
+            if (cg - 1 >= 0 && cg - 1 < P.n_sup) V += dw.x * Ub[(size_t)(cg - 1) * P.n_rho + q];
+            if (cg >= 0 && cg < P.n_sup) V += dw.y * Ub[(size_t)cg * P.n_rho + q];
+            if (cg + 1 >= 0 && cg + 1 < P.n_sup) V += dw.z * Ub[(size_t)(cg + 1) * P.n_rho + q];
+            if (cg + 2 >= 0 && cg + 2 < P.n_sup) V += dw.w * Ub[(size_t)(cg + 2) * P.n_rho + q];
+            float wx[4], wy[4];
+            bspline_w((float)(X - fx), wx);
+            bspline_w((float)(Y - fy), wy);
 #pragma unroll
-          for (int bb = 0; bb < 4; ++bb) {
-            const int ly = ky - 1 + bb - uy0;
-            if (ly < 0 || ly >= uy1 - uy0) continue;
-            const float vy = V * wy[bb];
+            for (int bb = 0; bb < 4; ++bb) {
+              const int ly = ky - 1 + bb - uy0;
+              if (ly < 0 || ly >= uy1 - uy0) continue;
+              const float vy = V * wy[bb];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-              const int lx = kx - 1 + a - ux0;
-              if (lx >= 0 && lx < ux1 - ux0) atomicAdd(&acc[ly][lx], vy * wx[a]);
+              for (int a = 0; a < 4; ++a) {
+                const int lx = kx - 1 + a - ux0;
+                if (lx >= 0 && lx < ux1 - ux0) atomicAdd(&acc[ly][lx], (double)(vy * wx[a]));
+              }
             }
           }
+          __syncthreads();
         }
       }
     }
@@ -232,7 +296,7 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
   float* dst = cbar + (size_t)b * n * n;
   for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
     const int ly = i / kTile, lx = i % kTile;
-    if (ty0 + ly < n && tx0 + lx < n) dst[(size_t)(ty0 + ly) * n + tx0 + lx] = acc[ly][lx];
+    if (ty0 + ly < n && tx0 + lx < n) dst[(size_t)(ty0 + ly) * n + tx0 + lx] = (float)acc[ly][lx];
   }
 }
 

@@ -66,72 +66,169 @@ rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int ba
 }
 
 // ------------------------------------------------------------------ cart -> log-polar
-constexpr int kSegRows = 16;  // coarse rows produced by one block
+constexpr int kFQ = 32;         // rho indices per block
+constexpr int kFRows = 16;      // coarse rows per block
+constexpr int kFPatch = 6144;   // floats of the LDS image patch
 
-// One thread per rho index q; the block walks the fine rows of kSegRows coarse rows (plus the
-// filter reach) in order, keeping the four coarse rows a fine row feeds in registers.
+// Bicubic sample of the spline coefficients at index position (X, Y); taps read through `tap`.
+template <class Tap>
+__device__ __forceinline__ float bicubic_at(double X, double Y, int n, Tap tap) {
+  const double fx = floor(X), fy = floor(Y);
+  float wx[4], wy[4];
+  bspline_w((float)(X - fx), wx);
+  bspline_w((float)(Y - fy), wy);
+  const int kx = min(max((int)fx, -1), n), ky = min(max((int)fy, -1), n);
+  float v = 0.f;
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb) {
+    float h = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) h += wx[a] * tap(kx - 1 + a, ky - 1 + bb);
+    v += wy[bb] * h;
+  }
+  return v;
+}
+
+// Block: kFQ consecutive rho indices and kFRows coarse rows of one (slice, partition).
+// 1) The fine rays feeding those rows sweep an annular sector of the image; its bounding box
+//    is staged in LDS (global gathers if it does not fit).  2) Each wave computes 8 x 8
+//    patches (8 fine rows x 8 rho indices, a compact footprint) of bicubic samples into an
+//    LDS buffer; samples outside D are zero.  3) Each coarse sample is the decimation filter
+//    over the fine rows around it, times e^rho.
 __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __restrict__ c, float* __restrict__ u) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= P.n_rho) return;
+  extern __shared__ float smem[];
+  float* patch = smem;
+  float* vbuf = smem + kFPatch;
+  const int q0 = blockIdx.x * kFQ;
   const int bm = blockIdx.z;
   const int b = bm / P.m, m = bm - b * P.m;
-  const int i0 = blockIdx.y * kSegRows;
-  const int i1 = min(i0 + kSegRows, P.n_sup);
+  const int i0 = blockIdx.y * kFRows;
+  const int i1 = min(i0 + kFRows, P.n_sup);
   const int n = P.n, r = P.r;
-  const double rho = (double)(q - P.n_rho + 1) * P.d_rho;
-  const double er = exp(rho);
-  const double E = er / (P.a_R * P.dx);
-  const float erf_ = (float)er;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const double X0 = P.X0[m], Y0 = P.Y0[m];
   const float* img = c + (size_t)b * n * n;
   const double2* cs = P.fine_cs + (size_t)m * P.n_fine;
   const int2* fq = P.fine_q + (size_t)m * P.n_fine;
-  float* urow = u + ((size_t)bm * P.n_sup) * P.n_rho + q;
-  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
-  for (int cg = i0 - 2; cg <= i1; ++cg) {
-    for (int ph = 0; ph < r; ++ph) {
-      const int ti = r * cg + ph - P.t_min;
-      float v = 0.f;
-      if (ti >= 0 && ti < P.n_fine) {
-        const int2 qr = fq[ti];
-        if (q >= qr.x && q <= qr.y) {
-          const double2 t = cs[ti];
-          const double X = X0 + E * t.x, Y = Y0 + E * t.y;
+  // fine rows t with |t - r i| < 2r for some i in [i0, i1)
+  const int tlo = r * (i0 - 2) + 1, thi = r * (i1 + 1) - 1;
+  const int nft = thi - tlo + 1;
+  const int tclo = max(tlo, P.t_min), tchi = min(thi, P.t_min + P.n_fine - 1);
+  const int qlast = min(q0 + kFQ, P.n_rho) - 1;
+  // any sample of the block inside D?
+  int inside = 0;
+  for (int t = tclo + (int)threadIdx.x; t <= tchi; t += blockDim.x) {
+    const int2 qr = fq[t - P.t_min];
+    inside |= (qr.x <= qr.y && qr.x <= qlast && qr.y >= q0);
+  }
+  inside = __syncthreads_or(inside);
+  int Xlo = 0, Ylo = 0, W = 0, H = 0;
+  bool staged = false;
+  if (inside) {
+    // bounding box of the sector: E in [erho[q0], erho[qlast]], directions of rays tclo..tchi
+    const double Elo = P.erho[q0], Ehi = P.erho[qlast];
+    const double2 ca = cs[tclo - P.t_min], cb2 = cs[tchi - P.t_min];
+    double xmin = fmin(fmin(Elo * ca.x, Ehi * ca.x), fmin(Elo * cb2.x, Ehi * cb2.x));
+    double xmax = fmax(fmax(Elo * ca.x, Ehi * ca.x), fmax(Elo * cb2.x, Ehi * cb2.x));
+    double ymin = fmin(fmin(Elo * ca.y, Ehi * ca.y), fmin(Elo * cb2.y, Ehi * cb2.y));
+    double ymax = fmax(fmax(Elo * ca.y, Ehi * ca.y), fmax(Elo * cb2.y, Ehi * cb2.y));
+    {
+      // the outer arc bulges past its chord where it crosses an axis direction
+      const double pa = atan2(ca.y, ca.x), pb = atan2(cb2.y, cb2.x);
+      const double lo = fmin(pa, pb), hi = fmax(pa, pb);
+      const double half_pi = 1.5707963267948966;
+      for (int k = -2; k <= 2; ++k) {
+        const double ax = k * half_pi;
+        if (ax > lo && ax < hi) {
+          const int kk = (k + 4) & 3;
+          if (kk == 0) xmax = fmax(xmax, Ehi);
+          if (kk == 2) xmin = fmin(xmin, -Ehi);
+          if (kk == 1) ymax = fmax(ymax, Ehi);
+          if (kk == 3) ymin = fmin(ymin, -Ehi);
+        }
+      }
+    }
+    Xlo = (int)floor(X0 + xmin) - 3;
+    Ylo = (int)floor(Y0 + ymin) - 3;
+    W = (int)floor(X0 + xmax) + 4 - Xlo + 1;
+    H = (int)floor(Y0 + ymax) + 4 - Ylo + 1;
+    staged = (long)W * H <= kFPatch;
+    if (staged) {
+      for (int idx = threadIdx.x; idx < W * H; idx += blockDim.x) {
+        const int ly = idx / W, lx = idx - ly * W;
+        int gy = (Ylo + ly) % n, gx = (Xlo + lx) % n;
+        gy += gy < 0 ? n : 0;
+        gx += gx < 0 ? n : 0;
+        patch[idx] = img[(size_t)gy * n + gx];
+      }
+    }
+  }
+  __syncthreads();
+  // fine samples, 8 x 8 patches per wave
+  const int npt = (nft + 7) >> 3;
+  const int npatch = npt * (kFQ / 8);
+  for (int pidx = wave; pidx < npatch; pidx += nwave) {
+    const int tl = (pidx / (kFQ / 8)) * 8 + (lane >> 3);
+    const int ql = (pidx % (kFQ / 8)) * 8 + (lane & 7);
+    if (tl >= nft) continue;
+    const int t = tlo + tl, q = q0 + ql;
+    float v = 0.f;
+    if (inside && t >= tclo && t <= tchi && q <= qlast) {
+      const int ti = t - P.t_min;
+      const int2 qr = fq[ti];
+      if (q >= qr.x && q <= qr.y) {
+        const double2 tc = cs[ti];
+        const double E = P.erho[q];
+        const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
+        if (staged) {
+          // the 4 x 4 taps start at (kx - 1, ky - 1); the patch holds them (clamped for safety)
           const double fx = floor(X), fy = floor(Y);
           float wx[4], wy[4];
           bspline_w((float)(X - fx), wx);
           bspline_w((float)(Y - fy), wy);
-          const int kx = min(max((int)fx, -1), n), ky = min(max((int)fy, -1), n);
-          int cx[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) cx[a] = wrap1(kx - 1 + a, n);
+          const int bx = min(max((int)fx - 1 - Xlo, 0), W - 4);
+          const int by = min(max((int)fy - 1 - Ylo, 0), H - 4);
+          const float* p0 = patch + by * W + bx;
 #pragma unroll
           for (int bb = 0; bb < 4; ++bb) {
-            const float* row = img + (size_t)wrap1(ky - 1 + bb, n) * n;
-            const float h = wx[0] * row[cx[0]] + wx[1] * row[cx[1]] + wx[2] * row[cx[2]] + wx[3] * row[cx[3]];
-            v += wy[bb] * h;
+            const float* pr = p0 + bb * W;
+            v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
           }
+        } else {
+          v = bicubic_at(X, Y, n, [&](int x, int y) { return img[(size_t)wrap1(y, n) * n + wrap1(x, n)]; });
         }
       }
-      const float4 dw = P.dec[ph];
-      acc0 += dw.x * v;
-      acc1 += dw.y * v;
-      acc2 += dw.z * v;
-      acc3 += dw.w * v;
     }
-    const int row = cg - 1;
-    if (row >= i0 && row < i1) urow[(size_t)row * P.n_rho] = acc0 * erf_;
-    acc0 = acc1;
-    acc1 = acc2;
-    acc2 = acc3;
-    acc3 = 0.f;
+    vbuf[tl * kFQ + ql] = v;
+  }
+  __syncthreads();
+  // decimation: u[i][q] = e^rho_q sum_n d_n v[r i + n][q]
+  const int nd = 4 * r - 1;
+  for (int o = threadIdx.x; o < (i1 - i0) * kFQ; o += blockDim.x) {
+    const int il = o / kFQ, ql = o - il * kFQ;
+    const int q = q0 + ql;
+    if (q > qlast) continue;
+    const int i = i0 + il;
+    const float* vcol = vbuf + (r * i - (2 * r - 1) - tlo) * kFQ + ql;
+    float acc = 0.f;
+    for (int k = 0; k < nd; ++k) acc += P.dtap[k] * vcol[k * kFQ];
+    const float er = (float)(P.erho[q] * (P.a_R * P.dx));
+    u[((size_t)bm * P.n_sup + i) * P.n_rho + q] = acc * er;
   }
 }
 
 rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
-  dim3 grid((d.n_rho + kThreads - 1) / kThreads, (d.n_sup + kSegRows - 1) / kSegRows, batch * d.m);
-  RL_LAUNCH("k_cart2lp", k_cart2lp, grid, dim3(kThreads), 0, s, d, c, u);
+  const int nft = d.r * (kFRows + 3) - 1;
+  const size_t lds = (size_t)(kFPatch + nft * kFQ) * sizeof(float);
+  if (lds > 65536) {
+    rl_status st = check_hip(hipFuncSetAttribute((const void*)k_cart2lp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds),
+                             "hipFuncSetAttribute(k_cart2lp)");
+    if (st != RL_OK) return st;
+  }
+  dim3 grid((d.n_rho + kFQ - 1) / kFQ, (d.n_sup + kFRows - 1) / kFRows, batch * d.m);
+  RL_LAUNCH("k_cart2lp", k_cart2lp, grid, dim3(kThreads), lds, s, d, c, u);
   return check_launch("k_cart2lp");
 }
 

@@ -378,6 +378,11 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
     for (int p = 0; p < r; ++p)
       dec[p] = make_float4((float)dn(p + r), (float)dn(p), (float)dn(p - r), (float)dn(p - 2 * r));
   }
+  std::vector<float> dtap(4 * r - 1);
+  for (int k = 0; k < 4 * r - 1; ++k) {
+    const int nn = k - (2 * r - 1);
+    dtap[k] = (float)(bspline((double)nn / r) / r);
+  }
   std::vector<int> own_j((size_t)M * n_own, -1);
   std::vector<double> own_cos((size_t)M * n_own, 1.0);
   for (int p = 0; p < M; ++p)
@@ -411,6 +416,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
       ramp[k] = (float)(acc / lr);
     }
   }
+  std::vector<double> erho(g.n_rho);
+  for (int q = 0; q < g.n_rho; ++q) erho[q] = std::exp((double)(q - g.n_rho + 1) * d.d_rho) / (a_R * d.dx);
   std::vector<float> pref(kPrefR + 1);
   {
     const double z = std::sqrt(3.0) - 2.0;
@@ -450,6 +457,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   const size_t o_tw = off; off += al(sizeof(float2) * tw.size());
   const size_t o_rp = off; off += al(sizeof(float) * ramp.size());
   const size_t o_pf = off; off += al(sizeof(float) * pref.size());
+  const size_t o_er = off; off += al(sizeof(double) * erho.size());
+  const size_t o_dt = off; off += al(sizeof(float) * dtap.size());
   const size_t table_bytes = off;
   // scratch for the quadrature (freed before returning)
   const size_t s_u = 0, s_a = al(sizeof(double) * n_nodes_pad), s_l = 2 * s_a, s_z = 3 * s_a;
@@ -516,6 +525,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
       {o_tw, tw.data(), sizeof(float2) * tw.size()},
       {o_rp, ramp.data(), sizeof(float) * ramp.size()},
       {o_pf, pref.data(), sizeof(float) * pref.size()},
+      {o_er, erho.data(), sizeof(double) * erho.size()},
+      {o_dt, dtap.data(), sizeof(float) * dtap.size()},
   };
   for (auto& up : ups)
     if ((st = check_hip(hipMemcpy(mem + up.off, up.src, up.bytes, hipMemcpyHostToDevice), "upload table")) != RL_OK)
@@ -529,6 +540,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   d.tw = (const float2*)(mem + o_tw);
   d.ramp = (const float*)(mem + o_rp);
   d.pref = (const float*)(mem + o_pf);
+  d.erho = (const double*)(mem + o_er);
+  d.dtap = (const float*)(mem + o_dt);
   plan->d_mem = mem;
   plan->d_mem_bytes = table_bytes;
   cleanup(RL_OK);

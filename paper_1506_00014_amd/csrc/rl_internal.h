@@ -16,7 +16,7 @@ constexpr int kHalo = 2;          // coarse rows on each side of a partition's o
 constexpr int kThreads = 256;     // threads per block of every hot-path kernel
 constexpr int kRowVals = 16;      // complex values per thread in a row FFT (N_rho/2 <= 4096)
 constexpr int kColVals = 32;      // complex values per thread in the theta pass
-constexpr int kTile = 32;         // image tile side of the adjoint splat
+constexpr int kTile = 64;         // image tile side of the adjoint splat
 constexpr int kPrefR = 16;        // half-length of the truncated prefilter (|z|^17 ~ 2e-10)
 constexpr int kMaxPart = 16;      // largest supported M
 
@@ -36,6 +36,8 @@ struct DevPlan {
   const float2* tw;        // [tw_len] exp(-2 pi i n / tw_len)
   const float* ramp;       // [lr/2 + 1] ramp multiplier (real), includes 1/lr
   const float* pref;       // [kPrefR + 1] prefilter taps sqrt(3) z^|k|
+  const double* erho;      // [n_rho] e^{rho_q} / (a_R dx): image-index length of the ray at rho_q
+  const float* dtap;       // [4r - 1] decimation taps d_n, n = -(2r-1) .. 2r-1
 };
 
 }  // namespace rl
