@@ -63,6 +63,7 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
   __syncthreads();
   const float inv_aR = (float)(1.0 / aR);
   const double base = (1.0 - aR) * cth;
+  const double scale_e = aR * P.dx;
   for (int q = threadIdx.x; q < nr; q += blockDim.x) {
     float acc = 0.f;
 #pragma unroll
@@ -70,8 +71,12 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
       const int qu = q + sh3 * nr;
       if (qu < -2 || qu > nr + 1) continue;
       // sinogram samples with tau in (qu - 2, qu + 2)
-      const double slo = (exp(P.rho0 + (qu - 2) * P.d_rho) - base) / aR;
-      const double shi = (exp(P.rho0 + (qu + 2) * P.d_rho) - base) / aR;
+      // e^{rho} at rho-index qu -/+ 2 (the table holds e^{rho_q} / (a_R dx) on [0, n_rho))
+      const int ql = min(max(qu - 2, 0), nr - 1), qh = min(max(qu + 2, 0), nr - 1);
+      const double elo = (qu - 2 == ql) ? P.erho[ql] * scale_e : exp(P.rho0 + (qu - 2) * P.d_rho);
+      const double ehi = (qu + 2 == qh) ? P.erho[qh] * scale_e : exp(P.rho0 + (qu + 2) * P.d_rho);
+      const double slo = (elo - base) / aR;
+      const double shi = (ehi - base) / aR;
       double ka, kb;
       if (!wrap) {
         ka = (slo + 1.0) / P.ds;
@@ -146,6 +151,7 @@ __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : 
 // threads walk them: each sample is rebuilt from the coarse rows by the transposed
 // decimation filter and spread with the 16 bicubic weights into the LDS tile.
 constexpr int kARows = 512;  // rays listed per pass
+constexpr int kStride = 3;   // lane stride along a ray in the adjoint splat
 
 __device__ __forceinline__ int block_exclusive_scan(int* buf, int nitems) {
   // in-place exclusive scan of buf[0..nitems), nitems <= 2 * blockDim.x; returns the total
@@ -175,6 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
   __shared__ double acc[kTile][kTile + 1];  // FP64: LDS float atomics are slow on this target
   __shared__ int rq0[kARows];
   __shared__ int rpre[kARows + 1];
+  __shared__ int rcnt[kARows];
   __shared__ double2 rcs[kARows];
   const int n = P.n, r = P.r;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
@@ -246,19 +253,25 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
               }
             }
             rq0[k] = qa;
-            rpre[k] = cnt;
+            rcnt[k] = cnt;
+            rpre[k] = kStride * ((cnt + kStride - 1) / kStride);  // padded to a multiple of the stride
             rcs[k] = tcs;
           }
           __syncthreads();
           const int total = block_exclusive_scan(rpre, nrows);
           if (threadIdx.x == 0) rpre[nrows] = total;
           __syncthreads();
-          // 2) walk the flattened samples
+          // 2) walk the flattened samples; within a ray, consecutive lanes take samples kStride
+          //    apart so that a wave's atomics fall on distinct pixels
           int k = 0;
           for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
             while (rpre[k + 1] <= idx) ++k;
+            const int pos = idx - rpre[k];
+            const int per = (rpre[k + 1] - rpre[k]) / kStride;
+            const int jj = kStride * (pos % per) + pos / per;
+            if (jj >= rcnt[k]) continue;
             const int t = tc + k;
-            const int q = rq0[k] + (idx - rpre[k]);
+            const int q = rq0[k] + jj;
             const double2 tcs = rcs[k];
             const double E = P.erho[q];
             const double X = X0 + E * tcs.x, Y = Y0 + E * tcs.y;

@@ -183,6 +183,57 @@ __device__ __forceinline__ void irfft_pre(float2* Z, int nc, const float2* __res
   }
 }
 
+// In-register FFT of compile-time power-of-two length R (radix-2, decimation in time with a
+// compile-time bit reversal).  Unnormalised; forward uses exp(-2 pi i jk/R), INV the
+// conjugate.  Twiddles are read from the plan's table tw[n] = exp(-2 pi i n / tw_len).
+template <int R>
+constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1, j = R >> 1; b < R; b <<= 1, j >>= 1)
+    if (i & b) r |= j;
+  return r;
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void reg_fft(float2 (&v)[R], const float2* __restrict__ tw, int tw_len) {
+  if constexpr (R == 1) {
+    return;
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int j = bitrev<R>(i);
+      if (i < j) {
+        const float2 t = v[i];
+        v[i] = v[j];
+        v[j] = t;
+      }
+    }
+    const int tstep = tw_len / R;
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+      const int half = len >> 1;
+#pragma unroll
+      for (int k = 0; k < half; ++k) {
+        const int e = k * (R / len);  // exponent in units of 1/R turns
+        float2 w;
+        if (e == 0) {
+          w = make_float2(1.f, 0.f);
+        } else {
+          w = tw[e * tstep];
+          if (INV) w.y = -w.y;
+        }
+#pragma unroll
+        for (int i = 0; i < R; i += len) {
+          const float2 a = v[i + k];
+          const float2 b = (e == 0) ? v[i + k + half] : cmul(v[i + k + half], w);
+          v[i + k] = cadd(a, b);
+          v[i + k + half] = csub(a, b);
+        }
+      }
+    }
+  }
+}
+
 // Cubic B-spline weights for taps k-1, k, k+1, k+2 at fractional offset a in [0, 1).
 __device__ __forceinline__ void bspline_w(float a, float* w) {
   const float a2 = a * a, a3 = a2 * a;

@@ -274,54 +274,132 @@ rl_status launch_irfft_rows(const rl_plan* p, const float2* in, float* out, int 
 }
 
 // ------------------------------------------------------------------ theta convolution
-// Block: CW spectrum columns of one (slice, partition).  LDS holds the CW columns as
-// contiguous length-K vectors; rows outside the input range are zero.
+// Four-step FFT of length K = K1 K2 along theta for CW spectrum columns of one
+// (slice, partition), with the multiplier applied between the forward and inverse K2-point
+// stages, so that the whole convolution makes two LDS round trips:
+//   A   thread (n2, c): x[n1] = in[K2 n1 + n2]; K1-point FFT over n1; times W_K^{n2 k1} -> LDS
+//   B   thread (k1, c): K2-point FFT over n2 (-> k = k1 + K1 k2); times H (or conj H);
+//       inverse K2-point FFT -> LDS
+//   A'  thread (n2, c): times W_K^{-n2 k1}; inverse K1-point FFT -> out rows K2 n1 + n2
+// Rows outside the input range are zero; only the requested output rows are written.
+template <int K1, int K2>
 __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2* __restrict__ in, int in_rows,
                                                          int in_off, float2* __restrict__ out, int out_rows,
                                                          int out_off, int conj, int cw) {
   extern __shared__ float2 sh[];
-  const int K = P.k_theta, nkt = K / 2 + 1, ncol = P.nc + 1;
+  constexpr int K = K1 * K2;
+  constexpr int RS = K2 + 1;           // padded stride between k1 rows
+  constexpr int CS = K1 * RS + 1;      // padded stride between columns
+  const int nkt = K / 2 + 1, ncol = P.nc + 1;
   const int bm = blockIdx.y;
   const int col0 = blockIdx.x * cw;
+  const int tw_step = P.tw_len / K;
   const float2* src = in + (size_t)bm * in_rows * P.ld;
-  for (int idx = threadIdx.x; idx < cw * K; idx += blockDim.x) {
-    const int cl = idx % cw, row = idx / cw;
-    const int col = col0 + cl;
-    const int ir = row - in_off;
-    float2 v = make_float2(0.f, 0.f);
-    if (col < ncol && ir >= 0 && ir < in_rows) v = src[(size_t)ir * P.ld + col];
-    sh[cl * K + row] = v;
-  }
-  __syncthreads();
-  fft_lds<kColVals, false>(sh, K, cw, P.tw, P.tw_len);
-  for (int idx = threadIdx.x; idx < cw * K; idx += blockDim.x) {
-    const int cl = idx / K, kt = idx % K;
-    const int col = col0 + cl;
-    if (col < ncol) {
-      const int akt = kt <= K / 2 ? kt : K - kt;
-      float2 h = P.H[(size_t)col * nkt + akt];
-      if (conj) h.y = -h.y;
-      sh[idx] = cmul(sh[idx], h);
+  // stage A
+  {
+    const int c = threadIdx.x % cw, n2 = threadIdx.x / cw;
+    const int col = col0 + c;
+    if (n2 < K2 && col < ncol) {
+      float2 x[K1];
+#pragma unroll
+      for (int n1 = 0; n1 < K1; ++n1) {
+        const int ir = K2 * n1 + n2 - in_off;
+        x[n1] = (ir >= 0 && ir < in_rows) ? src[(size_t)ir * P.ld + col] : make_float2(0.f, 0.f);
+      }
+      reg_fft<K1, false>(x, P.tw, P.tw_len);
+      float2* T = sh + c * CS;
+#pragma unroll
+      for (int k1 = 0; k1 < K1; ++k1) {
+        const float2 v = (k1 == 0 || n2 == 0) ? x[k1] : cmul(x[k1], P.tw[(n2 * k1) * tw_step]);
+        T[k1 * RS + n2] = v;
+      }
     }
   }
   __syncthreads();
-  fft_lds<kColVals, true>(sh, K, cw, P.tw, P.tw_len);
-  float2* dst = out + (size_t)bm * out_rows * P.ld;
-  for (int idx = threadIdx.x; idx < cw * out_rows; idx += blockDim.x) {
-    const int cl = idx % cw, orow = idx / cw;
-    const int col = col0 + cl;
-    if (col < ncol) dst[(size_t)orow * P.ld + col] = sh[cl * K + orow + out_off];
+  // stage B
+  {
+    const int c = threadIdx.x % cw, k1 = threadIdx.x / cw;
+    const int col = col0 + c;
+    if (k1 < K1 && col < ncol) {
+      float2* T = sh + c * CS + k1 * RS;
+      float2 y[K2];
+#pragma unroll
+      for (int n2 = 0; n2 < K2; ++n2) y[n2] = T[n2];
+      reg_fft<K2, false>(y, P.tw, P.tw_len);
+      const float2* Hc = P.H + (size_t)col * nkt;
+#pragma unroll
+      for (int k2 = 0; k2 < K2; ++k2) {
+        const int kt = k1 + K1 * k2;
+        float2 h = Hc[kt <= K / 2 ? kt : K - kt];
+        if (conj) h.y = -h.y;
+        y[k2] = cmul(y[k2], h);
+      }
+      reg_fft<K2, true>(y, P.tw, P.tw_len);
+#pragma unroll
+      for (int n2 = 0; n2 < K2; ++n2) T[n2] = y[n2];
+    }
   }
+  __syncthreads();
+  // stage A'
+  {
+    const int c = threadIdx.x % cw, n2 = threadIdx.x / cw;
+    const int col = col0 + c;
+    if (n2 < K2 && col < ncol) {
+      const float2* T = sh + c * CS;
+      float2 x[K1];
+#pragma unroll
+      for (int k1 = 0; k1 < K1; ++k1) {
+        float2 v = T[k1 * RS + n2];
+        if (k1 != 0 && n2 != 0) {
+          float2 w = P.tw[(n2 * k1) * tw_step];
+          w.y = -w.y;
+          v = cmul(v, w);
+        }
+        x[k1] = v;
+      }
+      reg_fft<K1, true>(x, P.tw, P.tw_len);
+      float2* dst = out + (size_t)bm * out_rows * P.ld;
+#pragma unroll
+      for (int n1 = 0; n1 < K1; ++n1) {
+        const int orow = K2 * n1 + n2 - out_off;
+        if (orow >= 0 && orow < out_rows) dst[(size_t)orow * P.ld + col] = x[n1];
+      }
+    }
+  }
+}
+
+template <int K1, int K2>
+static rl_status launch_theta_conv_t(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out,
+                                     int out_rows, int out_off, bool conj, int batch, hipStream_t s) {
+  const DevPlan& d = p->d;
+  const int cw = max(1, min(8, kThreads / max(K1, K2)));
+  const size_t lds = (size_t)cw * (K1 * (K2 + 1) + 1) * sizeof(float2);
+  if (lds > 65536) {
+    rl_status st = check_hip(hipFuncSetAttribute((const void*)k_theta_conv<K1, K2>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                             "hipFuncSetAttribute(k_theta_conv)");
+    if (st != RL_OK) return st;
+  }
+  dim3 grid((d.nc + 1 + cw - 1) / cw, batch * d.m);
+  RL_LAUNCH("k_theta_conv", (k_theta_conv<K1, K2>), grid, dim3(kThreads), lds, s, d, in, in_rows, in_off, out,
+            out_rows, out_off, conj ? 1 : 0, cw);
+  return check_launch("k_theta_conv");
 }
 
 rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out, int out_rows,
                             int out_off, bool conj, int batch, hipStream_t s) {
-  const DevPlan& d = p->d;
-  const int cw = (kColVals * kThreads) / d.k_theta >= 8 ? 8 : (kColVals * kThreads) / d.k_theta;
-  dim3 grid((d.nc + 1 + cw - 1) / cw, batch * d.m);
-  RL_LAUNCH("k_theta_conv", k_theta_conv, grid, dim3(kThreads), (size_t)cw * d.k_theta * sizeof(float2), s, d, in,
-                     in_rows, in_off, out, out_rows, out_off, conj ? 1 : 0, cw);
-  return check_launch("k_theta_conv");
+  switch (p->d.k_theta) {
+    case 8: return launch_theta_conv_t<8, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
+    case 16: return launch_theta_conv_t<16, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
+    case 32: return launch_theta_conv_t<32, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
+    case 64: return launch_theta_conv_t<32, 2>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
+    case 128: return launch_theta_conv_t<32, 4>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
+    case 256: return launch_theta_conv_t<32, 8>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
+    case 512: return launch_theta_conv_t<32, 16>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
+    case 1024: return launch_theta_conv_t<32, 32>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
+    case 2048: return launch_theta_conv_t<32, 64>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
+    default: return fail(RL_ERR_INTERNAL, "unsupported k_theta");
+  }
 }
 
 // ------------------------------------------------------------------ inverse rho FFT + evaluation

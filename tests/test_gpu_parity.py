@@ -66,6 +66,32 @@ CASES = [
     (16, 24, 16, 4, {}),      # smaller than one tile
 ]
 
+# larger theta-FFT lengths (K = 512, 1024, 2048) and the 1024 x 1024 configuration
+BIG_CASES = [
+    (256, 1024, 256, 4, {}),
+    (512, 2048, 512, 4, {}),
+    (256, 4096, 256, 4, {}),
+    (1024, 1024, 1024, 4, {}),
+]
+
+
+@pytest.mark.parametrize("case", BIG_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
+def test_forward_adjoint_parity_large(dev, case):
+    n, nt, ns, m, kw = case
+    plan, og = get_plan(n, nt, ns, m, **kw)
+    img, blobs_e, blobs_g = inputs.mixed_phantom(n, 30, 5, 201)
+    got = plan.forward(to_dev(img, dev)).cpu().numpy()
+    ref = oradon.radon_fwd(og, f32(img))
+    e = rel(got, ref)
+    print(f"R {case} K={og.k_theta}: rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
+    g = inputs.normal_array((nt, ns), 202)
+    got = plan.adjoint(to_dev(g, dev)).cpu().numpy()
+    ref = oradon.radon_adj(og, f32(g))
+    e = rel(got, ref)
+    print(f"R# {case} K={og.k_theta}: rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
+
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
 def test_forward_parity(dev, case):
