@@ -14,6 +14,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--no-cpu
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -54,10 +55,70 @@ def kernel_bytes(name, g, n_own, batch):
     return per_slice[name] * batch + extra
 
 
-def cpu_baseline(g, seed=303):
-    """The FP64 oracle on one of the M partitions of one slice: R, R# and the FBP filter.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2048x2048_b64.txt")
 
-    Per-slice time = prefilters + M x (partition forward + partition transpose) + ramp."""
+
+def source_digest():
+    """SHA-256 over the HIP sources and the C header: counters taken on other sources are stale."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1506_00014_amd", "csrc")
+    files = sorted(os.path.join(csrc, x) for x in os.listdir(csrc) if x.endswith((".hip", ".h")))
+    files.append(os.path.join(ROOT, "include", "radonlp.h"))
+    for fn in files:
+        h.update(os.path.basename(fn).encode())
+        with open(fn, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, batch, n):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, each scaled by what the same counter reads for a plain device copy of known size.
+    None if the summary is absent, is for another workload, or the sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        if ln.startswith("    ") or ":" not in ln or ln.startswith("#"):
+            continue
+        k, v = ln.split(":", 1)
+        kv[k.strip()] = v.strip()
+    try:
+        if kv["source_sha256"] != source_digest() or int(kv["batch"]) != batch or int(kv["n"]) != n:
+            return None
+        copy_bytes = float(kv["copy_bytes"])
+        f_scale = copy_bytes / (1024.0 * float(kv["copy_fetch_kib"]))
+        w_scale = copy_bytes / (1024.0 * float(kv["copy_write_kib"]))
+        fetch = 1024.0 * float(kv[f"{kernel}_fetch_kib"]) * f_scale
+        write = 1024.0 * float(kv[f"{kernel}_write_kib"]) * w_scale
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+    return {"bytes": round(fetch + write), "fetch": round(fetch), "write": round(write),
+            "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)}
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of known size, run under rocprofv3 --pmc to calibrate
+    FETCH_SIZE and WRITE_SIZE (bytes the counter reports per byte actually moved)."""
+    import torch
+
+    torch.cuda.set_device(0)
+    src = torch.rand(nbytes // 4, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def cpu_baseline(g, seed=303, parts=3):
+    """The FP64 oracle on `parts` of the M partitions of one slice: R, R# and the FBP filter.
+
+    Per-slice time = prefilters + M x (mean partition forward + mean partition transpose) + ramp."""
     import numpy as np
 
     from oracle import bspline, radon as oradon
@@ -65,6 +126,8 @@ def cpu_baseline(g, seed=303):
     from paper_1506_00014_amd import inputs
 
     og = Geometry(g["n"], g["n_theta"], g["n_s"], g["m"], g["n_rho"], g["k_theta"], g["r_dec"]).validate()
+    M = og.m
+    parts = min(parts, M)
     f = inputs.uniform_image(g["n"], seed)
     t0 = time.perf_counter()
     oradon._H(og)  # plan-time kernel table, not part of the sample
@@ -72,33 +135,35 @@ def cpu_baseline(g, seed=303):
     t0 = time.perf_counter()
     c = bspline.prefilter_2d(f)
     t_q = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    clp = oradon._partition_forward(og, c, 0, "fft")
     gpart = np.zeros((og.n_theta, og.n_s))
-    for i, j, tau in oradon.eval_taus(og, 0):
-        gpart[j] = bspline.eval_periodic_1d(clp[i], tau) / og.a_R
-    t_fwd = time.perf_counter() - t0
+    t_fwd = t_adj = 0.0
+    for p in range(parts):
+        t0 = time.perf_counter()
+        clp = oradon._partition_forward(og, c, p, "fft")
+        for i, j, tau in oradon.eval_taus(og, p):
+            gpart[j] = bspline.eval_periodic_1d(clp[i], tau) / og.a_R
+        t_fwd += time.perf_counter() - t0
     t0 = time.perf_counter()
-    w = oradon.ramp_filter(og, gpart)
-    t_ramp_part = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    cb = oradon._partition_adjoint(og, gpart, 0, "fft")
-    t_adj = time.perf_counter() - t0
-    del w, cb
-    M = og.m
-    t_ramp = t_ramp_part  # ramp_filter runs over every sinogram row
+    w = oradon.ramp_filter(og, gpart)  # ramp_filter runs over every sinogram row
+    t_ramp = time.perf_counter() - t0
+    for p in range(parts):
+        t0 = time.perf_counter()
+        oradon._partition_adjoint(og, gpart, p, "fft")
+        t_adj += time.perf_counter() - t0
+    del w
+    fwd, adj = t_fwd / parts, t_adj / parts
     # one step per slice: R (Q + M partitions), R# (M partitions + Q), FBP (ramp + M partitions + Q)
-    per_slice = (t_q + M * t_fwd) + (M * t_adj + t_q) + (t_ramp + M * t_adj + t_q)
-    sample = t_q + t_fwd + t_adj + t_ramp_part
+    per_slice = (t_q + M * fwd) + (M * adj + t_q) + (t_ramp + M * adj + t_q)
+    sample = t_q + t_fwd + t_adj + t_ramp
     return {
         "value": 1.0 / per_slice,
         "unit": "slices/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"partition 0 of {M} of one {g['n']}x{g['n']} slice ({g['n_theta']}x{g['n_s']} sinogram): "
-                   f"prefilter {t_q:.2f}s, partition forward {t_fwd:.2f}s, partition transpose {t_adj:.2f}s, "
-                   f"ramp on its rows {t_ramp_part:.2f}s; {sample:.1f}s of CPU work scaled to one step per slice "
-                   f"(R + R# + FBP = 3 prefilters + {M} forward + {2 * M} transposed partitions + ramp); "
+        "sample": (f"partitions 0..{parts - 1} of {M} of one {g['n']}x{g['n']} slice ({g['n_theta']}x{g['n_s']} "
+                   f"sinogram): prefilter {t_q:.2f}s, partition forward {fwd:.2f}s and partition transpose "
+                   f"{adj:.2f}s each (mean), ramp {t_ramp:.2f}s; {sample:.1f}s of CPU work scaled to one step "
+                   f"per slice (R + R# + FBP = 3 prefilters + {M} forward + {2 * M} transposed partitions + ramp); "
                    f"plan-time kernel table {t_plan:.1f}s excluded; numpy FP64, single thread"),
     }
 
@@ -112,7 +177,12 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (FETCH_SIZE / WRITE_SIZE calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); slices are independent, so "
               "a multi-GPU run would shard the batch with no communication.", file=sys.stderr)
@@ -184,8 +254,12 @@ def main():
                           "alg_bytes_per_launch": by, "alg_GBps": round(by / (avg * 1e-3) / 1e9, 1)}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     dk = kernels[dom]
+    tr = measured_traffic(dom, B, n)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dk["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(dk["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": tr["bytes"] if tr else None,
+                "alg_bytes": dk["alg_bytes_per_launch"]}
+    if tr:
+        roofline["traffic_detail"] = tr
 
     # per-operator rates, batched vs plain
     def time_op(fn, reps):
@@ -241,7 +315,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline(g)
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=1):  # numpy's BLAS on one thread, as the sample states
+            out["cpu_baseline"] = cpu_baseline(g)
     out["detail"] = detail
     print(json.dumps(out))
 

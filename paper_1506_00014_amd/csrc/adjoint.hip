@@ -64,6 +64,9 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
   const float inv_aR = (float)(1.0 / aR);
   const double base = (1.0 - aR) * cth;
   const double scale_e = aR * P.dx;
+  // the k range only selects candidates (the exact test is on the stored taps), so
+  // reciprocal multiplies are enough here
+  const double inv_aR_d = 1.0 / aR, inv_ds = 1.0 / P.ds;
   for (int q = threadIdx.x; q < nr; q += blockDim.x) {
     float acc = 0.f;
 #pragma unroll
@@ -75,15 +78,15 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
       const int ql = min(max(qu - 2, 0), nr - 1), qh = min(max(qu + 2, 0), nr - 1);
       const double elo = (qu - 2 == ql) ? P.erho[ql] * scale_e : exp(P.rho0 + (qu - 2) * P.d_rho);
       const double ehi = (qu + 2 == qh) ? P.erho[qh] * scale_e : exp(P.rho0 + (qu + 2) * P.d_rho);
-      const double slo = (elo - base) / aR;
-      const double shi = (ehi - base) / aR;
+      const double slo = (elo - base) * inv_aR_d;
+      const double shi = (ehi - base) * inv_aR_d;
       double ka, kb;
       if (!wrap) {
-        ka = (slo + 1.0) / P.ds;
-        kb = (shi + 1.0) / P.ds;
+        ka = (slo + 1.0) * inv_ds;
+        kb = (shi + 1.0) * inv_ds;
       } else {
-        ka = (1.0 - shi) / P.ds;
-        kb = (1.0 - slo) / P.ds;
+        ka = (1.0 - shi) * inv_ds;
+        kb = (1.0 - slo) * inv_ds;
       }
       // clamp in double before converting (NaN or huge bounds give an empty or full range)
       const int k0 = (int)fmin(fmax(floor(ka) - 1.0, 0.0), (double)ns);
@@ -150,7 +153,7 @@ __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : 
 // the ray's range inside D.  A block-wide scan then flattens the (ray, rho) samples, and all
 // threads walk them: each sample is rebuilt from the coarse rows by the transposed
 // decimation filter and spread with the 16 bicubic weights into the LDS tile.
-constexpr int kARows = 512;  // rays listed per pass
+constexpr int kARows = 256;  // rays listed per pass
 constexpr int kStride = 3;   // lane stride along a ray in the adjoint splat
 
 __device__ __forceinline__ int block_exclusive_scan(int* buf, int nitems) {
@@ -178,10 +181,14 @@ __device__ __forceinline__ int block_exclusive_scan(int* buf, int nitems) {
 
 __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float* __restrict__ U,
                                                           float* __restrict__ cbar) {
-  __shared__ double acc[kTile][kTile + 1];  // FP64: LDS float atomics are slow on this target
+  // FP64: LDS float atomics are slow on this target.  The pitch kTile + 2 keeps rows, columns
+  // and both diagonals of the tile spread over the LDS banks.
+  __shared__ double acc[kTile][kTile + 2];
   __shared__ int rq0[kARows];
   __shared__ int rpre[kARows + 1];
   __shared__ int rcnt[kARows];
+  __shared__ int rcg[kARows];
+  __shared__ float4 rdw[kARows];
   __shared__ double2 rcs[kARows];
   const int n = P.n, r = P.r;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
@@ -256,6 +263,10 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
             rcnt[k] = cnt;
             rpre[k] = kStride * ((cnt + kStride - 1) / kStride);  // padded to a multiple of the stride
             rcs[k] = tcs;
+            const int t = tc + k;
+            const int cg = floordiv(t, r);
+            rcg[k] = cg;
+            rdw[k] = P.dec[t - r * cg];
           }
           __syncthreads();
           const int total = block_exclusive_scan(rpre, nrows);
@@ -267,10 +278,10 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
           for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
             while (rpre[k + 1] <= idx) ++k;
             const int pos = idx - rpre[k];
-            const int per = (rpre[k + 1] - rpre[k]) / kStride;
-            const int jj = kStride * (pos % per) + pos / per;
+            const int per = (rpre[k + 1] - rpre[k]) / kStride;  // kStride is a compile-time 3
+            const int ph = (pos >= per) + (pos >= 2 * per);
+            const int jj = kStride * (pos - ph * per) + ph;
             if (jj >= rcnt[k]) continue;
-            const int t = tc + k;
             const int q = rq0[k] + jj;
             const double2 tcs = rcs[k];
             const double E = P.erho[q];
@@ -278,8 +289,8 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
             const double fx = floor(X), fy = floor(Y);
             const int kx = min(max((int)fx, -1), n), ky = min(max((int)fy, -1), n);
             if (kx + 2 < ux0 || kx - 1 >= ux1 || ky + 2 < uy0 || ky - 1 >= uy1) continue;
-            const int cg = floordiv(t, r);
-            const float4 dw = P.dec[t - r * cg];
+            const int cg = rcg[k];
+            const float4 dw = rdw[k];
             float V = 0.f;
             if (cg - 1 >= 0 && cg - 1 < P.n_sup) V += dw.x * Ub[(size_t)(cg - 1) * P.n_rho + q];
             if (cg >= 0 && cg < P.n_sup) V += dw.y * Ub[(size_t)cg * P.n_rho + q];

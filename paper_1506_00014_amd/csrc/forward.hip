@@ -39,22 +39,41 @@ __global__ __launch_bounds__(kThreads) void k_prefilter(const float* __restrict_
     tin[ly][lx] = src[(size_t)gy * n + gx];
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < kPI * kPT; idx += blockDim.x) {
-    const int ly = idx / kPT, lx = idx % kPT;
-    float acc = q[0] * tin[ly][lx + kPrefR];
+  float qk[kPrefR + 1];
 #pragma unroll
-    for (int k = 1; k <= kPrefR; ++k) acc += q[k] * (tin[ly][lx + kPrefR - k] + tin[ly][lx + kPrefR + k]);
-    trow[ly][lx] = acc;
+  for (int k = 0; k <= kPrefR; ++k) qk[k] = q[k];
+  // rows: each thread filters 8 consecutive outputs of one row from a register window
+  {
+    constexpr int R = 8;
+    const int row = threadIdx.x / (kPT / R), seg = threadIdx.x % (kPT / R);
+    float x[R + 2 * kPrefR];
+#pragma unroll
+    for (int i = 0; i < R + 2 * kPrefR; ++i) x[i] = tin[row][seg * R + i];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      float acc = qk[0] * x[j + kPrefR];
+#pragma unroll
+      for (int k = 1; k <= kPrefR; ++k) acc += qk[k] * (x[j + kPrefR - k] + x[j + kPrefR + k]);
+      trow[row][seg * R + j] = acc;
+    }
   }
   __syncthreads();
+  // columns: each thread filters 4 consecutive outputs of one column
   float* dst = out + (size_t)b * n * n;
-  for (int idx = threadIdx.x; idx < kPT * kPT; idx += blockDim.x) {
-    const int ly = idx / kPT, lx = idx % kPT;
-    float acc = q[0] * trow[ly + kPrefR][lx];
+  {
+    constexpr int R = 4;
+    const int col = threadIdx.x % kPT, seg = threadIdx.x / kPT;
+    float y[R + 2 * kPrefR];
 #pragma unroll
-    for (int k = 1; k <= kPrefR; ++k) acc += q[k] * (trow[ly + kPrefR - k][lx] + trow[ly + kPrefR + k][lx]);
-    const int gy = ty0 + ly, gx = tx0 + lx;
-    if (gy < n && gx < n) dst[(size_t)gy * n + gx] = acc * scale;
+    for (int i = 0; i < R + 2 * kPrefR; ++i) y[i] = trow[seg * R + i][col];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      float acc = qk[0] * y[j + kPrefR];
+#pragma unroll
+      for (int k = 1; k <= kPrefR; ++k) acc += qk[k] * (y[j + kPrefR - k] + y[j + kPrefR + k]);
+      const int gy = ty0 + seg * R + j, gx = tx0 + col;
+      if (gy < n && gx < n) dst[(size_t)gy * n + gx] = acc * scale;
+    }
   }
 }
 
@@ -122,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
     inside |= (qr.x <= qr.y && qr.x <= qlast && qr.y >= q0);
   }
   inside = __syncthreads_or(inside);
-  int Xlo = 0, Ylo = 0, W = 0, H = 0;
+  int Xlo = 0, Ylo = 0, W = 0, H = 0, Wp = 1;
   bool staged = false;
   if (inside) {
     // bounding box of the sector: E in [erho[q0], erho[qlast]], directions of rays tclo..tchi
@@ -152,14 +171,15 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
     Ylo = (int)floor(Y0 + ymin) - 3;
     W = (int)floor(X0 + xmax) + 4 - Xlo + 1;
     H = (int)floor(Y0 + ymax) + 4 - Ylo + 1;
-    staged = (long)W * H <= kFPatch;
+    Wp = W | 1;  // odd pitch spreads rows over the LDS banks
+    staged = (long)Wp * H <= kFPatch;
     if (staged) {
       for (int idx = threadIdx.x; idx < W * H; idx += blockDim.x) {
         const int ly = idx / W, lx = idx - ly * W;
         int gy = (Ylo + ly) % n, gx = (Xlo + lx) % n;
         gy += gy < 0 ? n : 0;
         gx += gx < 0 ? n : 0;
-        patch[idx] = img[(size_t)gy * n + gx];
+        patch[ly * Wp + lx] = img[(size_t)gy * n + gx];
       }
     }
   }
@@ -188,10 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
           bspline_w((float)(Y - fy), wy);
           const int bx = min(max((int)fx - 1 - Xlo, 0), W - 4);
           const int by = min(max((int)fy - 1 - Ylo, 0), H - 4);
-          const float* p0 = patch + by * W + bx;
+          const float* p0 = patch + by * Wp + bx;
 #pragma unroll
           for (int bb = 0; bb < 4; ++bb) {
-            const float* pr = p0 + bb * W;
+            const float* pr = p0 + bb * Wp;
             v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
           }
         } else {
