@@ -6,7 +6,7 @@
 //                  along rho
 //   k_theta_conv   (shared with the forward) with the conjugate multiplier
 //   k_irfft_scale  inverse real FFT along rho of every support row, times e^rho (step 5)
-//   k_lp2cart_adj  transpose of steps 3-4: per 32x32 image tile, every fine log-polar
+//   k_lp2cart_adj  transpose of steps 3-4: per 64x64 image tile, every fine log-polar
 //                  sample whose bicubic footprint meets the tile is rebuilt from the coarse
 //                  rows by the decimation filter and spread into LDS with the same 16
 //                  weights the forward gathers with; partitions are summed in the tile
@@ -148,53 +148,182 @@ __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : 
 // Block: one kTile x kTile image tile.  For every partition, the fine log-polar rays that
 // cross the tile are listed first (one thread per ray): a ray t is the half-line
 // x* + E (cos psi_t, sin psi_t) in image-index coordinates (x* = T_m^{-1}(0),
-// E = e^rho / (a_R dx)); the rho indices whose bicubic footprint can reach the tile are
-// those where the ray crosses the tile grown by two pixels (slab test), intersected with
-// the ray's range inside D.  A block-wide scan then flattens the (ray, rho) samples, and all
-// threads walk them: each sample is rebuilt from the coarse rows by the transposed
-// decimation filter and spread with the 16 bicubic weights into the LDS tile.
-constexpr int kARows = 256;  // rays listed per pass
-constexpr int kStride = 3;   // lane stride along a ray in the adjoint splat
+// E = e^rho / (a_R dx)).  A slab test against the tile grown by two pixels gives a range of
+// rho indices (intersected with the ray's range inside D), which is then trimmed at both
+// ends to exactly the samples whose 4 x 4 bicubic footprint meets the tile (the footprint
+// origin floor(X) moves monotonically along a ray, so those samples are contiguous).  The
+// ranges are cut into segments of kSeg samples and numbered by a block-wide scan with the
+// rays taken kRayGap apart (rays t, t + kRayGap, ... first), so that the threads of a wave,
+// which walk consecutive segments in lockstep, sit on rays kRayGap apart or kSeg samples
+// apart on one ray: their footprints are then mostly disjoint and each LDS add of a wave
+// spreads over the banks.  Each sample is rebuilt from the coarse rows by the transposed
+// decimation filter; its 16 weighted values are summed in registers into the walking
+// thread's 4 x 4 footprint.  Along a ray the footprint origin floor(X), floor(Y) advances by
+// at most one pixel per sample for the usual geometries, so the footprint is kept oriented
+// along the ray's direction and, when it advances, only its trailing column or row is added
+// to the LDS tile (any other move adds all of it).  The FP64 LDS tile has a halo of kAHalo
+// pixels that holds every footprint, so the adds need no bounds tests.
+constexpr int kAThreads = 512;  // threads of the adjoint splat
+constexpr int kARows = 128;     // rays listed per pass
+constexpr int kSeg = 16;        // rho indices per segment
+constexpr int kRayGap = 8;      // rays of one lane group are kRayGap apart
+constexpr int kASlots = kARows + kRayGap;  // ray slots per pass (groups padded to equal size)
+constexpr int kAHalo = 3;       // halo of the LDS tile: footprints reach 3 pixels before and 2 after
+constexpr int kAW = kTile + 2 * kAHalo;  // LDS tile side
+constexpr int kAP = kAW + 1;             // LDS tile pitch (odd)
+constexpr int kUCap = 5120;     // floats of the LDS copy of the coarse rows a pass reads
+constexpr int kECap = 512;      // rho indices of the LDS copy of e^rho
 
-__device__ __forceinline__ int block_exclusive_scan(int* buf, int nitems) {
-  // in-place exclusive scan of buf[0..nitems), nitems <= 2 * blockDim.x; returns the total
-  __shared__ int part[kThreads];
-  const int t = threadIdx.x;
-  const int a = 2 * t < nitems ? buf[2 * t] : 0;
-  const int b = 2 * t + 1 < nitems ? buf[2 * t + 1] : 0;
-  part[t] = a + b;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    const int v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+// In-place exclusive scan of buf[0..nitems), nitems <= 3 * 64, by the first wave alone (no
+// block barriers inside); returns the total to that wave.  Callers synchronise around it.
+__device__ __forceinline__ int wave_exclusive_scan(int* buf, int nitems) {
+  const int lane = threadIdx.x & 63;
+  int v[3], s = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int k = 3 * lane + i;
+    v[i] = k < nitems ? buf[k] : 0;
+    s += v[i];
   }
-  const int incl = part[t];
-  const int excl = incl - (a + b);
-  if (2 * t < nitems) buf[2 * t] = excl;
-  if (2 * t + 1 < nitems) buf[2 * t + 1] = excl + a;
-  const int total = part[blockDim.x - 1];
-  __syncthreads();
-  return total;
+  int incl = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  int run = incl - s;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int k = 3 * lane + i;
+    if (k < nitems) buf[k] = run;
+    run += v[i];
+  }
+  return __shfl(incl, 63, 64);
 }
 
-__global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float* __restrict__ U,
-                                                          float* __restrict__ cbar) {
-  // FP64: LDS float atomics are slow on this target.  The pitch kTile + 2 keeps rows, columns
-  // and both diagonals of the tile spread over the LDS banks.
-  __shared__ double acc[kTile][kTile + 2];
-  __shared__ int rq0[kARows];
-  __shared__ int rpre[kARows + 1];
-  __shared__ int rcnt[kARows];
-  __shared__ int rcg[kARows];
-  __shared__ float4 rdw[kARows];
-  __shared__ double2 rcs[kARows];
+// Everything one thread needs to walk one segment of a ray.
+struct SegWalk {
+  double X0, Y0;       // x* in image-index coordinates
+  double cx, cy;       // ray direction
+  int qbeg, qend;      // rho indices of the segment (inclusive)
+  int ux0, ux1, uy0, uy1;  // tile [ux0, ux1) x [uy0, uy1) in unwrapped index coordinates
+  float dw[4];         // decimation weights of the coarse rows (0 for rows outside the support)
+  int roff[4];         // offsets of those rows in the row store read
+};
+
+// Walk one segment: rebuild every sample from the coarse rows, sum its bicubic weights into
+// the register footprint, and add to the LDS tile what the footprint leaves behind.  Rows
+// and e^rho come from their LDS copies, indexed from rho index qlo.
+__device__ __forceinline__ void splat_walk(const SegWalk& sw, double* acc, const float* rows, const double* erho,
+                                           int qlo) {
+  // footprint in the ray's orientation: w[j][i] is the pixel i columns and j rows from the
+  // trailing corner (x = kx - 1 + i or kx + 2 - i as the ray runs towards +x or -x; likewise
+  // for y), so it always advances by dropping w[.][0] or w[0][.]; weights in that order are
+  // the cubic B-spline weights at the fraction measured from the other side (the weights are
+  // symmetric: w_k(a) = w_{3-k}(1 - a))
+  const bool xp = sw.cx >= 0.0, yp = sw.cy >= 0.0;
+  const int cstep = xp ? 1 : -1, rstep = yp ? kAP : -kAP;
+  auto corner = [&](int kx, int ky) {
+    const int x = xp ? kx - 1 : kx + 2, y = yp ? ky - 1 : ky + 2;
+    return (y - sw.uy0 + kAHalo) * kAP + (x - sw.ux0 + kAHalo);
+  };
+  float w[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[j][i] = 0.f;
+  int ckx = 0, cky = 0;
+  for (int q = sw.qbeg; q <= sw.qend; ++q) {
+    const int qi = q - qlo;
+    const double E = erho[qi];
+    const float V = sw.dw[0] * rows[sw.roff[0] + qi] + sw.dw[1] * rows[sw.roff[1] + qi] +
+                    sw.dw[2] * rows[sw.roff[2] + qi] + sw.dw[3] * rows[sw.roff[3] + qi];
+    const double X = sw.X0 + E * sw.cx, Y = sw.Y0 + E * sw.cy;
+    const double fx = floor(X), fy = floor(Y);
+    // the trimmed range keeps kx in [ux0 - 2, ux1] and ky in [uy0 - 2, uy1]; the clamp only
+    // keeps the adds inside the tile should that ever fail
+    const int kx = min(max((int)fx, sw.ux0 - 2), sw.ux1), ky = min(max((int)fy, sw.uy0 - 2), sw.uy1);
+    if (q == sw.qbeg) {
+      ckx = kx;
+      cky = ky;
+    } else {
+      const int dx = xp ? kx - ckx : ckx - kx, dy = yp ? ky - cky : cky - ky;
+      if ((unsigned)dx > 1u || (unsigned)dy > 1u) {
+        const int o = corner(ckx, cky);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            atomicAdd(acc + o + j * rstep + i * cstep, (double)w[j][i]);
+            w[j][i] = 0.f;
+          }
+        ckx = kx;
+        cky = ky;
+      } else {
+        if (dx) {
+          const int o = corner(ckx, cky);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            atomicAdd(acc + o + j * rstep, (double)w[j][0]);
+            w[j][0] = w[j][1];
+            w[j][1] = w[j][2];
+            w[j][2] = w[j][3];
+            w[j][3] = 0.f;
+          }
+          ckx = kx;
+        }
+        if (dy) {
+          const int o = corner(ckx, cky);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            atomicAdd(acc + o + i * cstep, (double)w[0][i]);
+            w[0][i] = w[1][i];
+            w[1][i] = w[2][i];
+            w[2][i] = w[3][i];
+            w[3][i] = 0.f;
+          }
+          cky = ky;
+        }
+      }
+    }
+    const float ax = (float)(X - fx), ay = (float)(Y - fy);
+    float wx[4], wy[4];
+    bspline_w(xp ? ax : 1.0f - ax, wx);
+    bspline_w(yp ? ay : 1.0f - ay, wy);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float vy = V * wy[j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[j][i] += vy * wx[i];
+    }
+  }
+  if (sw.qend >= sw.qbeg) {
+    const int o = corner(ckx, cky);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) atomicAdd(acc + o + j * rstep + i * cstep, (double)w[j][i]);
+  }
+}
+
+__global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const float* __restrict__ U,
+                                                              float* __restrict__ cbar) {
+  // FP64: LDS float atomics are slow on this target.
+  __shared__ double acc[kAW * kAP];
+  // per ray slot (slot of ray k of a pass: (k % kRayGap) * ng + k / kRayGap)
+  __shared__ int rq0[kASlots];
+  __shared__ int rpre[kASlots + 1];
+  __shared__ int rcnt[kASlots];
+  __shared__ int rcg[kASlots];
+  __shared__ float4 rdw[kASlots];
+  __shared__ double2 rcs[kASlots];
+  __shared__ float us[kUCap];   // coarse rows [cg0, cg0 + nur) x rho indices [qlo, qlo + span)
+  __shared__ double es[kECap];  // e^{rho_q} / (a_R dx) for q in [qlo, qlo + span)
+  __shared__ int qext[2];
   const int n = P.n, r = P.r;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
   const int b = blockIdx.z;
-  for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) acc[i / kTile][i % kTile] = 0.0;
-  __syncthreads();
+  for (int i = threadIdx.x; i < kAW * kAP; i += blockDim.x) acc[i] = 0.0;
   const int txe = min(tx0 + kTile, n), tye = min(ty0 + kTile, n);
   for (int m = 0; m < P.m; ++m) {
     const double cb = cos(m * P.beta), sb = sin(m * P.beta);
@@ -229,89 +358,146 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
         const int tb = min(P.t_min + P.n_fine - 1, (int)ceil((phmax - P.phi0[m]) / fstep) + 1);
         for (int tc = ta; tc <= tb; tc += kARows) {
           const int nrows = min(kARows, tb - tc + 1);
-          // 1) rho range of each ray inside the grown tile and inside D
-          for (int k = threadIdx.x; k < nrows; k += blockDim.x) {
-            const int ti = tc + k - P.t_min;
-            const int2 qr = fq[ti];
-            const double2 tcs = cs[ti];
-            int cnt = 0, qa = 0;
-            if (qr.x <= qr.y) {
-              double elo = 0.0, ehi = 1e300;
-              bool ok = true;
-              if (fabs(tcs.x) > 1e-15) {
-                const double e1 = (Xa - X0) / tcs.x, e2 = (Xb - X0) / tcs.x;
-                elo = fmax(elo, fmin(e1, e2));
-                ehi = fmin(ehi, fmax(e1, e2));
-              } else {
-                ok = ok && X0 >= Xa && X0 <= Xb;
-              }
-              if (fabs(tcs.y) > 1e-15) {
-                const double e1 = (Ya - Y0) / tcs.y, e2 = (Yb - Y0) / tcs.y;
-                elo = fmax(elo, fmin(e1, e2));
-                ehi = fmin(ehi, fmax(e1, e2));
-              } else {
-                ok = ok && Y0 >= Ya && Y0 <= Yb;
-              }
-              if (ok && elo <= ehi && ehi > 0.0) {
-                const double scale = P.a_R * P.dx;
-                qa = max(qr.x, (int)floor(log(fmax(elo * scale, 1e-300)) / P.d_rho + P.n_rho - 1) - 1);
-                const int qb = min(qr.y, (int)ceil(log(ehi * scale) / P.d_rho + P.n_rho - 1) + 1);
-                cnt = max(0, qb - qa + 1);
-              }
-            }
-            rq0[k] = qa;
-            rcnt[k] = cnt;
-            rpre[k] = kStride * ((cnt + kStride - 1) / kStride);  // padded to a multiple of the stride
-            rcs[k] = tcs;
-            const int t = tc + k;
-            const int cg = floordiv(t, r);
-            rcg[k] = cg;
-            rdw[k] = P.dec[t - r * cg];
+          const int ng = (nrows + kRayGap - 1) / kRayGap;  // slots per group
+          const int nslot = ng * kRayGap;
+          if (threadIdx.x == 0) {
+            qext[0] = 0x7fffffff;
+            qext[1] = -0x7fffffff;
           }
           __syncthreads();
-          const int total = block_exclusive_scan(rpre, nrows);
-          if (threadIdx.x == 0) rpre[nrows] = total;
-          __syncthreads();
-          // 2) walk the flattened samples; within a ray, consecutive lanes take samples kStride
-          //    apart so that a wave's atomics fall on distinct pixels
-          int k = 0;
-          for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-            while (rpre[k + 1] <= idx) ++k;
-            const int pos = idx - rpre[k];
-            const int per = (rpre[k + 1] - rpre[k]) / kStride;  // kStride is a compile-time 3
-            const int ph = (pos >= per) + (pos >= 2 * per);
-            const int jj = kStride * (pos - ph * per) + ph;
-            if (jj >= rcnt[k]) continue;
-            const int q = rq0[k] + jj;
-            const double2 tcs = rcs[k];
-            const double E = P.erho[q];
-            const double X = X0 + E * tcs.x, Y = Y0 + E * tcs.y;
-            const double fx = floor(X), fy = floor(Y);
-            const int kx = min(max((int)fx, -1), n), ky = min(max((int)fy, -1), n);
-            if (kx + 2 < ux0 || kx - 1 >= ux1 || ky + 2 < uy0 || ky - 1 >= uy1) continue;
-            const int cg = rcg[k];
-            const float4 dw = rdw[k];
-            float V = 0.f;
-            if (cg - 1 >= 0 && cg - 1 < P.n_sup) V += dw.x * Ub[(size_t)(cg - 1) * P.n_rho + q];
-            if (cg >= 0 && cg < P.n_sup) V += dw.y * Ub[(size_t)cg * P.n_rho + q];
-            if (cg + 1 >= 0 && cg + 1 < P.n_sup) V += dw.z * Ub[(size_t)(cg + 1) * P.n_rho + q];
-            if (cg + 2 >= 0 && cg + 2 < P.n_sup) V += dw.w * Ub[(size_t)(cg + 2) * P.n_rho + q];
-            float wx[4], wy[4];
-            bspline_w((float)(X - fx), wx);
-            bspline_w((float)(Y - fy), wy);
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb) {
-              const int ly = ky - 1 + bb - uy0;
-              if (ly < 0 || ly >= uy1 - uy0) continue;
-              const float vy = V * wy[bb];
-#pragma unroll
-              for (int a = 0; a < 4; ++a) {
-                const int lx = kx - 1 + a - ux0;
-                if (lx >= 0 && lx < ux1 - ux0) atomicAdd(&acc[ly][lx], (double)(vy * wx[a]));
+          // 1) rho range of each ray inside the grown tile (slab test) and inside D, trimmed
+          //    to the samples whose footprint meets the tile
+          for (int sl = threadIdx.x; sl < nslot; sl += blockDim.x) {
+            const int k = (sl % ng) * kRayGap + sl / ng;  // ray of slot sl
+            int qa = 0, qb = -1;
+            if (k < nrows) {
+              const int t = tc + k;
+              const int ti = t - P.t_min;
+              const int2 qr = fq[ti];
+              const double2 tcs = cs[ti];
+              const int cg = floordiv(t, r);
+              rcg[sl] = cg;
+              rdw[sl] = P.dec[t - r * cg];
+              rcs[sl] = tcs;
+              if (qr.x <= qr.y) {
+                double elo = 0.0, ehi = 1e300;
+                bool ok = true;
+                if (fabs(tcs.x) > 1e-15) {
+                  const double e1 = (Xa - X0) / tcs.x, e2 = (Xb - X0) / tcs.x;
+                  elo = fmax(elo, fmin(e1, e2));
+                  ehi = fmin(ehi, fmax(e1, e2));
+                } else {
+                  ok = ok && X0 >= Xa && X0 <= Xb;
+                }
+                if (fabs(tcs.y) > 1e-15) {
+                  const double e1 = (Ya - Y0) / tcs.y, e2 = (Yb - Y0) / tcs.y;
+                  elo = fmax(elo, fmin(e1, e2));
+                  ehi = fmin(ehi, fmax(e1, e2));
+                } else {
+                  ok = ok && Y0 >= Ya && Y0 <= Yb;
+                }
+                if (ok && elo <= ehi && ehi > 0.0) {
+                  const double scale = P.a_R * P.dx;
+                  qa = max(qr.x, (int)floor(log(fmax(elo * scale, 1e-300)) / P.d_rho + P.n_rho - 1) - 1);
+                  qb = min(qr.y, (int)ceil(log(ehi * scale) / P.d_rho + P.n_rho - 1) + 1);
+                }
+                // the footprint origin moves monotonically along the ray, so the samples whose
+                // footprint meets the tile are contiguous: trim both ends to them
+                auto meets = [&](int q) {
+                  const double E = P.erho[q];
+                  const int kx = min(max((int)floor(X0 + E * tcs.x), -1), n);
+                  const int ky = min(max((int)floor(Y0 + E * tcs.y), -1), n);
+                  return kx >= ux0 - 2 && kx <= ux1 && ky >= uy0 - 2 && ky <= uy1;
+                };
+                while (qa <= qb && !meets(qa)) ++qa;
+                while (qb >= qa && !meets(qb)) --qb;
               }
             }
+            const int cnt = qb - qa + 1;
+            if (cnt > 0) {
+              atomicMin(&qext[0], qa);
+              atomicMax(&qext[1], qb);
+            }
+            rq0[sl] = qa;
+            rcnt[sl] = qb;
+            rpre[sl] = cnt > 0 ? (cnt + kSeg - 1) / kSeg : 0;
           }
           __syncthreads();
+          if (threadIdx.x < 64) {
+            const int total = wave_exclusive_scan(rpre, nslot);
+            if (threadIdx.x == 0) rpre[nslot] = total;
+          }
+          __syncthreads();
+          const int total = rpre[nslot];
+          if (total == 0) continue;  // uniform; the loop head synchronises before the next pass
+          // 2) rho windows: the coarse rows cg - 1 .. cg + 2 of the pass's rays and e^rho are
+          //    copied to LDS (coalesced rows, all loads of a thread issued together) for one
+          //    window of rho indices at a time; one window usually covers the whole pass
+          const int qlo = qext[0], qhi = qext[1];
+          const int cg0 = max(floordiv(tc, r) - 1, 0);
+          const int cg1 = min(floordiv(tc + nrows - 1, r) + 2, P.n_sup - 1);
+          const int nur = cg1 - cg0 + 1;
+          const int wlen = min(kECap, kUCap / nur);
+          for (int wq = qlo; wq <= qhi; wq += wlen) {
+            const int span = min(wlen, qhi - wq + 1);
+            {
+              constexpr int kIt = (kUCap + kAThreads - 1) / kAThreads;
+              const int tot = nur * span;
+              float tmp[kIt];
+#pragma unroll
+              for (int it = 0; it < kIt; ++it) {
+                const int i = threadIdx.x + it * kAThreads;
+                const int row = i / span, qq = i - row * span;
+                tmp[it] = i < tot ? Ub[(size_t)(cg0 + row) * P.n_rho + wq + qq] : 0.f;
+              }
+              const double e = threadIdx.x < span ? P.erho[wq + threadIdx.x] : 0.0;
+#pragma unroll
+              for (int it = 0; it < kIt; ++it) {
+                const int i = threadIdx.x + it * kAThreads;
+                if (i < tot) us[i] = tmp[it];
+              }
+              if (threadIdx.x < span) es[threadIdx.x] = e;
+            }
+            __syncthreads();
+            // 3) walk whole segments (clipped to the window)
+            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+              // the slot holding segment idx: the last k with rpre[k] <= idx
+              int lo = 0, hi = nslot - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rpre[mid] <= idx) lo = mid;
+                else hi = mid - 1;
+              }
+              const int k = lo;
+              SegWalk sw;
+              sw.X0 = X0;
+              sw.Y0 = Y0;
+              const double2 tcs = rcs[k];
+              sw.cx = tcs.x;
+              sw.cy = tcs.y;
+              const int q0 = rq0[k] + (idx - rpre[k]) * kSeg;
+              sw.qbeg = max(q0, wq);
+              sw.qend = min(min(q0 + kSeg - 1, rcnt[k]), wq + span - 1);
+              sw.ux0 = ux0;
+              sw.ux1 = ux1;
+              sw.uy0 = uy0;
+              sw.uy1 = uy1;
+              const int cg = rcg[k];
+              const float4 dw = rdw[k];
+              const float dwv[4] = {dw.x, dw.y, dw.z, dw.w};
+              // coarse rows cg-1 .. cg+2 feed this ray; a row outside the support gets weight 0
+              // and reads a copied row instead
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int row = cg - 1 + i;
+                const bool ok = row >= 0 && row < P.n_sup;
+                sw.dw[i] = ok ? dwv[i] : 0.f;
+                sw.roff[i] = (min(max(row, cg0), cg1) - cg0) * span;
+              }
+              splat_walk(sw, acc, us, es, wq);
+            }
+            __syncthreads();
+          }
         }
       }
     }
@@ -320,14 +506,15 @@ __global__ __launch_bounds__(kThreads) void k_lp2cart_adj(DevPlan P, const float
   float* dst = cbar + (size_t)b * n * n;
   for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
     const int ly = i / kTile, lx = i % kTile;
-    if (ty0 + ly < n && tx0 + lx < n) dst[(size_t)(ty0 + ly) * n + tx0 + lx] = (float)acc[ly][lx];
+    if (ty0 + ly < n && tx0 + lx < n)
+      dst[(size_t)(ty0 + ly) * n + tx0 + lx] = (float)acc[(ly + kAHalo) * kAP + lx + kAHalo];
   }
 }
 
 rl_status launch_lp2cart_adj(const rl_plan* p, const float* U, float* cbar, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   dim3 grid((d.n + kTile - 1) / kTile, (d.n + kTile - 1) / kTile, batch);
-  RL_LAUNCH("k_lp2cart_adj", k_lp2cart_adj, grid, dim3(kThreads), 0, s, d, U, cbar);
+  RL_LAUNCH("k_lp2cart_adj", k_lp2cart_adj, grid, dim3(kAThreads), 0, s, d, U, cbar);
   return check_launch("k_lp2cart_adj");
 }
 
