@@ -29,11 +29,20 @@ __device__ __forceinline__ float bspline_w1(int a, float al) {
 }
 
 // ------------------------------------------------------------------ transpose of step 7
+// One owned row per block.  The forward evaluation reads, for every sinogram sample k, the
+// four periodic taps kq_k - 1 .. kq_k + 2 (kq_k = floor(tau_k)) of the log-polar row.  Its
+// transpose adds w_a(tau_k) g_k to tap a of each k.  tau is strictly monotone in k along a
+// row (increasing, or decreasing for the rows of theta near pi), so in the order of increasing
+// tau the samples feeding rho index q are consecutive: starting at the first sample with
+// kq >= q - 2 (a table built by a scatter in which every q has exactly one writer), a thread
+// per q sums them without atomics.  Taps that wrap around the row (kq <= 0 or kq >= n_rho - 2)
+// are added afterwards.  Then the real FFT of the row.
 __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float* __restrict__ sino,
                                                          float2* __restrict__ spec) {
   extern __shared__ float2 sh[];
   const int nc = P.nc, nr = P.n_rho, ns = P.n_s;
-  float* xs = reinterpret_cast<float*>(sh);
+  float* xs = reinterpret_cast<float*>(sh);   // n_rho reals (the FFT buffer)
+  int* kfirst = reinterpret_cast<int*>(sh);   // aliases xs: entry q is read before xs[q] is written
   float* gs = reinterpret_cast<float*>(sh + nc);
   int* kqs = reinterpret_cast<int*>(gs + ns);
   float* als = reinterpret_cast<float*>(kqs + ns);
@@ -51,52 +60,46 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
   const double cth = P.own_cos[m * P.n_own + o];
   const double aR = P.a_R;
   const float* src = sino + ((size_t)b * P.n_theta + j) * ns;
-  for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-    gs[k] = src[k];
+  // samples in order of increasing tau: position i holds sample k = wrap ? ns - 1 - i : i
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    const int k = wrap ? ns - 1 - i : i;
+    gs[i] = src[k];
     double s = -1.0 + k * P.ds;
     if (wrap) s = -s;
     const double tau = (log(aR * s + (1.0 - aR) * cth) - P.rho0) / P.d_rho;
     const double ft = floor(tau);
-    kqs[k] = min(max((int)ft, -1), nr);
-    als[k] = (float)(tau - ft);
+    kqs[i] = min(max((int)ft, -1), nr);
+    als[i] = (float)(tau - ft);
+  }
+  for (int q = threadIdx.x; q < nr; q += blockDim.x) kfirst[q] = ns;
+  __syncthreads();
+  // kfirst[q] = first i with kq_i >= q - 2: sample i is the first for q in (kq_{i-1} + 2, kq_i + 2]
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    const int lo = i == 0 ? 0 : max(kqs[i - 1] + 3, 0);
+    const int hi = min(kqs[i] + 2, nr - 1);
+    for (int q = lo; q <= hi; ++q) kfirst[q] = i;
   }
   __syncthreads();
   const float inv_aR = (float)(1.0 / aR);
-  const double base = (1.0 - aR) * cth;
-  const double scale_e = aR * P.dx;
-  // the k range only selects candidates (the exact test is on the stored taps), so
-  // reciprocal multiplies are enough here
-  const double inv_aR_d = 1.0 / aR, inv_ds = 1.0 / P.ds;
   for (int q = threadIdx.x; q < nr; q += blockDim.x) {
     float acc = 0.f;
-#pragma unroll
-    for (int sh3 = -1; sh3 <= 1; ++sh3) {
-      const int qu = q + sh3 * nr;
-      if (qu < -2 || qu > nr + 1) continue;
-      // sinogram samples with tau in (qu - 2, qu + 2)
-      // e^{rho} at rho-index qu -/+ 2 (the table holds e^{rho_q} / (a_R dx) on [0, n_rho))
-      const int ql = min(max(qu - 2, 0), nr - 1), qh = min(max(qu + 2, 0), nr - 1);
-      const double elo = (qu - 2 == ql) ? P.erho[ql] * scale_e : exp(P.rho0 + (qu - 2) * P.d_rho);
-      const double ehi = (qu + 2 == qh) ? P.erho[qh] * scale_e : exp(P.rho0 + (qu + 2) * P.d_rho);
-      const double slo = (elo - base) * inv_aR_d;
-      const double shi = (ehi - base) * inv_aR_d;
-      double ka, kb;
-      if (!wrap) {
-        ka = (slo + 1.0) * inv_ds;
-        kb = (shi + 1.0) * inv_ds;
-      } else {
-        ka = (1.0 - shi) * inv_ds;
-        kb = (1.0 - slo) * inv_ds;
-      }
-      // clamp in double before converting (NaN or huge bounds give an empty or full range)
-      const int k0 = (int)fmin(fmax(floor(ka) - 1.0, 0.0), (double)ns);
-      const int k1 = (int)fmax(fmin(ceil(kb) + 1.0, (double)(ns - 1)), -1.0);
-      for (int k = k0; k <= k1; ++k) {
-        const int a = qu - (kqs[k] - 1);
-        if (a >= 0 && a <= 3) acc += bspline_w1(a, als[k]) * gs[k];
-      }
+    for (int i = kfirst[q]; i < ns; ++i) {
+      const int a = q - (kqs[i] - 1);  // tap index of q for sample i; a <= 3 from kfirst
+      if (a < 0) break;
+      acc += bspline_w1(a, als[i]) * gs[i];
     }
     xs[q] = acc * inv_aR;
+  }
+  __syncthreads();
+  // taps beyond either end of the row wrap around (only samples with kq <= 0 or kq >= nr - 2)
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    const int kq = kqs[i];
+    if (kq > 0 && kq < nr - 2) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int t = kq - 1 + a;
+      if (t < 0 || t >= nr) atomicAdd(&xs[wrap1(t, nr)], bspline_w1(a, als[i]) * gs[i] * inv_aR);
+    }
   }
   __syncthreads();
   fft_lds<kRowVals, false>(sh, nc, 1, P.tw, P.tw_len);
@@ -152,10 +155,10 @@ __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : 
 // rho indices (intersected with the ray's range inside D), which is then trimmed at both
 // ends to exactly the samples whose 4 x 4 bicubic footprint meets the tile (the footprint
 // origin floor(X) moves monotonically along a ray, so those samples are contiguous).  The
-// ranges are cut into segments of kSeg samples and numbered by a block-wide scan with the
-// rays taken kRayGap apart (rays t, t + kRayGap, ... first), so that the threads of a wave,
-// which walk consecutive segments in lockstep, sit on rays kRayGap apart or kSeg samples
-// apart on one ray: their footprints are then mostly disjoint and each LDS add of a wave
+// ranges are cut into segments, long enough that every thread walks at most one, and
+// numbered by a scan with the rays taken kRayGap apart (rays t, t + kRayGap, ... first), so
+// that the threads of a wave, which walk consecutive segments in lockstep, sit on rays
+// kRayGap apart or a segment length apart on one ray: their footprints are then mostly disjoint and each LDS add of a wave
 // spreads over the banks.  Each sample is rebuilt from the coarse rows by the transposed
 // decimation filter; its 16 weighted values are summed in registers into the walking
 // thread's 4 x 4 footprint.  Along a ray the footprint origin floor(X), floor(Y) advances by
@@ -165,10 +168,11 @@ __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : 
 // pixels that holds every footprint, so the adds need no bounds tests.
 constexpr int kAThreads = 512;  // threads of the adjoint splat
 constexpr int kARows = 128;     // rays listed per pass
-constexpr int kSeg = 16;        // rho indices per segment
+constexpr int kSegMin = 8;      // shortest segment (rho indices)
 constexpr int kRayGap = 8;      // rays of one lane group are kRayGap apart
 constexpr int kASlots = kARows + kRayGap;  // ray slots per pass (groups padded to equal size)
-constexpr int kAHalo = 3;       // halo of the LDS tile: footprints reach 3 pixels before and 2 after
+constexpr int kAHalo = 4;       // halo of the LDS tile: footprints reach 3 pixels before and 2 after,
+                                // one more on each side covers the trim's rounding (see the trim)
 constexpr int kAW = kTile + 2 * kAHalo;  // LDS tile side
 constexpr int kAP = kAW + 1;             // LDS tile pitch (odd)
 constexpr int kUCap = 5120;     // floats of the LDS copy of the coarse rows a pass reads
@@ -240,9 +244,10 @@ __device__ __forceinline__ void splat_walk(const SegWalk& sw, double* acc, const
                     sw.dw[2] * rows[sw.roff[2] + qi] + sw.dw[3] * rows[sw.roff[3] + qi];
     const double X = sw.X0 + E * sw.cx, Y = sw.Y0 + E * sw.cy;
     const double fx = floor(X), fy = floor(Y);
-    // the trimmed range keeps kx in [ux0 - 2, ux1] and ky in [uy0 - 2, uy1]; the clamp only
-    // keeps the adds inside the tile should that ever fail
-    const int kx = min(max((int)fx, sw.ux0 - 2), sw.ux1), ky = min(max((int)fy, sw.uy0 - 2), sw.uy1);
+    // the trimmed range keeps kx in [ux0 - 2, ux1] and ky in [uy0 - 2, uy1], give or take the
+    // trim's rounding (one pixel, with zero weight on the tile); the clamp only keeps the adds
+    // inside the halo should that ever fail
+    const int kx = min(max((int)fx, sw.ux0 - 3), sw.ux1 + 1), ky = min(max((int)fy, sw.uy0 - 3), sw.uy1 + 1);
     if (q == sw.qbeg) {
       ckx = kx;
       cky = ky;
@@ -319,7 +324,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
   __shared__ double2 rcs[kASlots];
   __shared__ float us[kUCap];   // coarse rows [cg0, cg0 + nur) x rho indices [qlo, qlo + span)
   __shared__ double es[kECap];  // e^{rho_q} / (a_R dx) for q in [qlo, qlo + span)
-  __shared__ int qext[2];
+  __shared__ int qext[3];  // rho range of the pass; segment length
   const int n = P.n, r = P.r;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
   const int b = blockIdx.z;
@@ -345,13 +350,14 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
           const double ex = fmax(fmax(x1a, -x1b), 0.0), ey = fmax(fmax(x2a, -x2b), 0.0);
           if (ex * ex + ey * ey >= 1.0) continue;  // rectangle misses the unit disc
         }
-        // angular extent of the rectangle seen from x* (which lies outside it)
-        double phmin = 1e30, phmax = -1e30;
+        // angular extent of the rectangle seen from x* (which lies outside it); FP32 is ample:
+        // the ray range below is padded by one fine ray (~1e-4 rad or more)
+        float phmin = 1e30f, phmax = -1e30f;
         for (int c = 0; c < 4; ++c) {
           const double dX = ((c & 1) ? Xb : Xa) - X0, dY = ((c & 2) ? Yb : Ya) - Y0;
-          const double ph = atan2(-sb * dX + cb * dY, cb * dX + sb * dY);
-          phmin = fmin(phmin, ph);
-          phmax = fmax(phmax, ph);
+          const float ph = atan2f((float)(-sb * dX + cb * dY), (float)(cb * dX + sb * dY));
+          phmin = fminf(phmin, ph);
+          phmax = fmaxf(phmax, ph);
         }
         const double fstep = P.dtheta / r;
         const int ta = max(P.t_min, (int)floor((phmin - P.phi0[m]) / fstep) - 1);
@@ -380,6 +386,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
               rdw[sl] = P.dec[t - r * cg];
               rcs[sl] = tcs;
               if (qr.x <= qr.y) {
+                const double inv_aRdx = 1.0 / (P.a_R * P.dx);
                 double elo = 0.0, ehi = 1e300;
                 bool ok = true;
                 if (fabs(tcs.x) > 1e-15) {
@@ -402,9 +409,13 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
                   qb = min(qr.y, (int)ceil(log(ehi * scale) / P.d_rho + P.n_rho - 1) + 1);
                 }
                 // the footprint origin moves monotonically along the ray, so the samples whose
-                // footprint meets the tile are contiguous: trim both ends to them
+                // footprint meets the tile are contiguous: trim both ends to them.  E is
+                // recomputed here (no dependent table loads); should it differ from the table
+                // in the last bit and move floor(X) across an integer, the sample kept or
+                // dropped sits where its weights on the tile are zero, and its footprint stays
+                // within the halo
                 auto meets = [&](int q) {
-                  const double E = P.erho[q];
+                  const double E = exp(P.rho0 + q * P.d_rho) * inv_aRdx;
                   const int kx = min(max((int)floor(X0 + E * tcs.x), -1), n);
                   const int ky = min(max((int)floor(Y0 + E * tcs.y), -1), n);
                   return kx >= ux0 - 2 && kx <= ux1 && ky >= uy0 - 2 && ky <= uy1;
@@ -413,22 +424,39 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
                 while (qb >= qa && !meets(qb)) --qb;
               }
             }
-            const int cnt = qb - qa + 1;
+            const int cnt = max(qb - qa + 1, 0);
             if (cnt > 0) {
               atomicMin(&qext[0], qa);
               atomicMax(&qext[1], qb);
             }
             rq0[sl] = qa;
             rcnt[sl] = qb;
-            rpre[sl] = cnt > 0 ? (cnt + kSeg - 1) / kSeg : 0;
+            rpre[sl] = cnt;
           }
           __syncthreads();
+          // segment length: long enough that every thread walks at most one segment
+          // (sum over rays of ceil(cnt / len) <= samples / len + rays <= blockDim.x)
           if (threadIdx.x < 64) {
+            int ssum = 0, nray = 0;
+            for (int i = threadIdx.x; i < nslot; i += 64) {
+              ssum += rpre[i];
+              nray += rpre[i] > 0;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+              ssum += __shfl_xor(ssum, off, 64);
+              nray += __shfl_xor(nray, off, 64);
+            }
+            const int len = max(kSegMin, (ssum + (kAThreads - nray) - 1) / (kAThreads - nray));
+            for (int i = threadIdx.x; i < nslot; i += 64) rpre[i] = (rpre[i] + len - 1) / len;
             const int total = wave_exclusive_scan(rpre, nslot);
-            if (threadIdx.x == 0) rpre[nslot] = total;
+            if (threadIdx.x == 0) {
+              rpre[nslot] = total;
+              qext[2] = len;
+            }
           }
           __syncthreads();
-          const int total = rpre[nslot];
+          const int total = rpre[nslot], seglen = qext[2];
           if (total == 0) continue;  // uniform; the loop head synchronises before the next pass
           // 2) rho windows: the coarse rows cg - 1 .. cg + 2 of the pass's rays and e^rho are
           //    copied to LDS (coalesced rows, all loads of a thread issued together) for one
@@ -475,9 +503,9 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
               const double2 tcs = rcs[k];
               sw.cx = tcs.x;
               sw.cy = tcs.y;
-              const int q0 = rq0[k] + (idx - rpre[k]) * kSeg;
+              const int q0 = rq0[k] + (idx - rpre[k]) * seglen;
               sw.qbeg = max(q0, wq);
-              sw.qend = min(min(q0 + kSeg - 1, rcnt[k]), wq + span - 1);
+              sw.qend = min(min(q0 + seglen - 1, rcnt[k]), wq + span - 1);
               sw.ux0 = ux0;
               sw.ux1 = ux1;
               sw.uy0 = uy0;

@@ -86,7 +86,7 @@ rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int ba
 
 // ------------------------------------------------------------------ cart -> log-polar
 constexpr int kFQ = 32;         // rho indices per block
-constexpr int kFRows = 16;      // coarse rows per block
+constexpr int kFRows = 8;       // coarse rows per block
 constexpr int kFPatch = 6144;   // floats of the LDS image patch
 
 // Bicubic sample of the spline coefficients at index position (X, Y); taps read through `tap`.
@@ -132,14 +132,28 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
   // fine rows t with |t - r i| < 2r for some i in [i0, i1)
   const int tlo = r * (i0 - 2) + 1, thi = r * (i1 + 1) - 1;
   const int nft = thi - tlo + 1;
+  const int nftmax = r * (kFRows + 3) - 1;  // the launch sizes LDS for this many rows
+  // LDS copies of the block's ray table (direction, rho range inside D) and of e^rho
+  double2* scs = reinterpret_cast<double2*>(vbuf + nftmax * kFQ);
+  int2* sfq = reinterpret_cast<int2*>(scs + nftmax);
+  double* se = reinterpret_cast<double*>(sfq + nftmax);
   const int tclo = max(tlo, P.t_min), tchi = min(thi, P.t_min + P.n_fine - 1);
   const int qlast = min(q0 + kFQ, P.n_rho) - 1;
-  // any sample of the block inside D?
+  // stage the tables; is any sample of the block inside D?
   int inside = 0;
-  for (int t = tclo + (int)threadIdx.x; t <= tchi; t += blockDim.x) {
-    const int2 qr = fq[t - P.t_min];
+  for (int tl = threadIdx.x; tl < nft; tl += blockDim.x) {
+    const int t = tlo + tl;
+    int2 qr = make_int2(1, 0);  // empty
+    double2 tc = make_double2(0.0, 0.0);
+    if (t >= tclo && t <= tchi) {
+      qr = fq[t - P.t_min];
+      tc = cs[t - P.t_min];
+    }
+    sfq[tl] = qr;
+    scs[tl] = tc;
     inside |= (qr.x <= qr.y && qr.x <= qlast && qr.y >= q0);
   }
+  if (threadIdx.x < kFQ) se[threadIdx.x] = q0 + (int)threadIdx.x <= qlast ? P.erho[q0 + threadIdx.x] : 0.0;
   inside = __syncthreads_or(inside);
   int Xlo = 0, Ylo = 0, W = 0, H = 0, Wp = 1;
   bool staged = false;
@@ -193,12 +207,11 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
     if (tl >= nft) continue;
     const int t = tlo + tl, q = q0 + ql;
     float v = 0.f;
-    if (inside && t >= tclo && t <= tchi && q <= qlast) {
-      const int ti = t - P.t_min;
-      const int2 qr = fq[ti];
+    if (inside && q <= qlast) {
+      const int2 qr = sfq[tl];
       if (q >= qr.x && q <= qr.y) {
-        const double2 tc = cs[ti];
-        const double E = P.erho[q];
+        const double2 tc = scs[tl];
+        const double E = se[ql];
         const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
         if (staged) {
           // the 4 x 4 taps start at (kx - 1, ky - 1); the patch holds them (clamped for safety)
@@ -240,7 +253,8 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
 rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   const int nft = d.r * (kFRows + 3) - 1;
-  const size_t lds = (size_t)(kFPatch + nft * kFQ) * sizeof(float);
+  const size_t lds = (size_t)(kFPatch + nft * kFQ) * sizeof(float) + (size_t)nft * (sizeof(double2) + sizeof(int2)) +
+                     kFQ * sizeof(double);
   if (lds > 65536) {
     rl_status st = check_hip(hipFuncSetAttribute((const void*)k_cart2lp, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds),
