@@ -471,12 +471,21 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
             {
               constexpr int kIt = (kUCap + kAThreads - 1) / kAThreads;
               const int tot = nur * span;
+              // element i = threadIdx.x + it * kAThreads is (row, qq) = divmod(i, span); both
+              // advance by the block stride without a division per element
+              const int drow = kAThreads / span, dqq = kAThreads - drow * span;
+              int row = (int)threadIdx.x / span, qq = (int)threadIdx.x - row * span;
               float tmp[kIt];
 #pragma unroll
               for (int it = 0; it < kIt; ++it) {
                 const int i = threadIdx.x + it * kAThreads;
-                const int row = i / span, qq = i - row * span;
                 tmp[it] = i < tot ? Ub[(size_t)(cg0 + row) * P.n_rho + wq + qq] : 0.f;
+                row += drow;
+                qq += dqq;
+                if (qq >= span) {
+                  qq -= span;
+                  ++row;
+                }
               }
               const double e = threadIdx.x < span ? P.erho[wq + threadIdx.x] : 0.0;
 #pragma unroll

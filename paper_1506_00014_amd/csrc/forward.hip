@@ -188,12 +188,36 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
     Wp = W | 1;  // odd pitch spreads rows over the LDS banks
     staged = (long)Wp * H <= kFPatch;
     if (staged) {
-      for (int idx = threadIdx.x; idx < W * H; idx += blockDim.x) {
-        const int ly = idx / W, lx = idx - ly * W;
-        int gy = (Ylo + ly) % n, gx = (Xlo + lx) % n;
-        gy += gy < 0 ? n : 0;
-        gx += gx < 0 ? n : 0;
-        patch[ly * Wp + lx] = img[(size_t)gy * n + gx];
+      // flat element order; (ly, lx) advance by the block stride without a division per
+      // element, four loads in flight per thread; indices outside the image wrap
+      const int tot = W * H;
+      const int dly = (int)blockDim.x / W, dlx = (int)blockDim.x - dly * W;
+      int ly = (int)threadIdx.x / W, lx = (int)threadIdx.x - ly * W;
+      for (int base = 0; base < tot; base += 4 * (int)blockDim.x) {
+        float v[4];
+        int dsti[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
+          dsti[u] = -1;
+          v[u] = 0.f;
+          if (idx < tot) {
+            int gy = Ylo + ly, gx = Xlo + lx;
+            if (gy < 0 || gy >= n) gy = ((gy % n) + n) % n;
+            if (gx < 0 || gx >= n) gx = ((gx % n) + n) % n;
+            v[u] = img[(size_t)gy * n + gx];
+            dsti[u] = ly * Wp + lx;
+          }
+          ly += dly;
+          lx += dlx;
+          if (lx >= W) {
+            lx -= W;
+            ++ly;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (dsti[u] >= 0) patch[dsti[u]] = v[u];
       }
     }
   }
