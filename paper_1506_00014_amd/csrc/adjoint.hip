@@ -172,7 +172,7 @@ constexpr int kSegMin = 8;      // shortest segment (rho indices)
 constexpr int kRayGap = 8;      // rays of one lane group are kRayGap apart
 constexpr int kASlots = kARows + kRayGap;  // ray slots per pass (groups padded to equal size)
 constexpr int kAHalo = 4;       // halo of the LDS tile: footprints reach 3 pixels before and 2 after,
-                                // one more on each side covers the trim's rounding (see the trim)
+                                // one more on each side covers the range's rounding
 constexpr int kAW = kTile + 2 * kAHalo;  // LDS tile side
 constexpr int kAP = kAW + 1;             // LDS tile pitch (odd)
 constexpr int kUCap = 5120;     // floats of the LDS copy of the coarse rows a pass reads
@@ -371,8 +371,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
             qext[1] = -0x7fffffff;
           }
           __syncthreads();
-          // 1) rho range of each ray inside the grown tile (slab test) and inside D, trimmed
-          //    to the samples whose footprint meets the tile
+          // 1) rho range of each ray inside the grown tile (slab test) and inside D
           for (int sl = threadIdx.x; sl < nslot; sl += blockDim.x) {
             const int k = (sl % ng) * kRayGap + sl / ng;  // ray of slot sl
             int qa = 0, qb = -1;
@@ -386,7 +385,6 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
               rdw[sl] = P.dec[t - r * cg];
               rcs[sl] = tcs;
               if (qr.x <= qr.y) {
-                const double inv_aRdx = 1.0 / (P.a_R * P.dx);
                 double elo = 0.0, ehi = 1e300;
                 bool ok = true;
                 if (fabs(tcs.x) > 1e-15) {
@@ -403,25 +401,19 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
                 } else {
                   ok = ok && Y0 >= Ya && Y0 <= Yb;
                 }
+                // samples whose footprint meets the tile: floor(X) in [ux0 - 2, ux1] and floor(Y)
+                // in [uy0 - 2, uy1], i.e. the point inside the grown tile [Xa, Xb] x [Ya, Yb]
+                // (within D, X and Y lie in (0, n), so the clip to [0, n] changes nothing):
+                // E in [elo, ehi], rho indices from ceil(tau(elo)) to floor(tau(ehi)).  Rounding
+                // can only misplace a sample within ~1e-9 pixel of a footprint edge, where its
+                // weight on the tile is zero; the halo holds such a footprint
                 if (ok && elo <= ehi && ehi > 0.0) {
                   const double scale = P.a_R * P.dx;
-                  qa = max(qr.x, (int)floor(log(fmax(elo * scale, 1e-300)) / P.d_rho + P.n_rho - 1) - 1);
-                  qb = min(qr.y, (int)ceil(log(ehi * scale) / P.d_rho + P.n_rho - 1) + 1);
+                  const double tlo = log(fmax(elo * scale, 1e-300)) / P.d_rho + P.n_rho - 1;
+                  const double thi = log(ehi * scale) / P.d_rho + P.n_rho - 1;
+                  qa = (int)fmax(ceil(tlo), (double)qr.x);
+                  qb = (int)fmin(floor(thi), (double)qr.y);
                 }
-                // the footprint origin moves monotonically along the ray, so the samples whose
-                // footprint meets the tile are contiguous: trim both ends to them.  E is
-                // recomputed here (no dependent table loads); should it differ from the table
-                // in the last bit and move floor(X) across an integer, the sample kept or
-                // dropped sits where its weights on the tile are zero, and its footprint stays
-                // within the halo
-                auto meets = [&](int q) {
-                  const double E = exp(P.rho0 + q * P.d_rho) * inv_aRdx;
-                  const int kx = min(max((int)floor(X0 + E * tcs.x), -1), n);
-                  const int ky = min(max((int)floor(Y0 + E * tcs.y), -1), n);
-                  return kx >= ux0 - 2 && kx <= ux1 && ky >= uy0 - 2 && ky <= uy1;
-                };
-                while (qa <= qb && !meets(qa)) ++qa;
-                while (qb >= qa && !meets(qb)) --qb;
               }
             }
             const int cnt = max(qb - qa + 1, 0);
