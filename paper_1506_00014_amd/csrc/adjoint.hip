@@ -30,22 +30,15 @@ __device__ __forceinline__ float bspline_w1(int a, float al) {
 
 // ------------------------------------------------------------------ transpose of step 7
 // One owned row per block.  The forward evaluation reads, for every sinogram sample k, the
-// four periodic taps kq_k - 1 .. kq_k + 2 (kq_k = floor(tau_k)) of the log-polar row.  Its
-// transpose adds w_a(tau_k) g_k to tap a of each k.  tau is strictly monotone in k along a
-// row (increasing, or decreasing for the rows of theta near pi), so in the order of increasing
-// tau the samples feeding rho index q are consecutive: starting at the first sample with
-// kq >= q - 2 (a table built by a scatter in which every q has exactly one writer), a thread
-// per q sums them without atomics.  Taps that wrap around the row (kq <= 0 or kq >= n_rho - 2)
-// are added afterwards.  Then the real FFT of the row.
+// four periodic taps kq_k - 1 .. kq_k + 2 (kq_k = floor(tau_k)) of the log-polar row; its
+// transpose adds w_a(tau_k) g_k / a_R to tap a.  Each thread adds the taps of its samples to
+// an FP64 row in LDS (FP64 LDS atomics are fast on this target; where tau moves by more than
+// one rho step from sample to sample, as usual, the lanes of one add hit distinct entries).  The row is
+// then converted to FP32 in place and real-FFT'd.
 __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float* __restrict__ sino,
                                                          float2* __restrict__ spec) {
-  extern __shared__ float2 sh[];
+  extern __shared__ double acc[];  // n_rho entries; reused as the FP32 FFT buffer
   const int nc = P.nc, nr = P.n_rho, ns = P.n_s;
-  float* xs = reinterpret_cast<float*>(sh);   // n_rho reals (the FFT buffer)
-  int* kfirst = reinterpret_cast<int*>(sh);   // aliases xs: entry q is read before xs[q] is written
-  float* gs = reinterpret_cast<float*>(sh + nc);
-  int* kqs = reinterpret_cast<int*>(gs + ns);
-  float* als = reinterpret_cast<float*>(kqs + ns);
   const int o = blockIdx.x;
   const int bm = blockIdx.y;
   const int b = bm / P.m, m = bm - b * P.m;
@@ -59,56 +52,47 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
   const bool wrap = (jw >> 30) & 1;
   const double cth = P.own_cos[m * P.n_own + o];
   const double aR = P.a_R;
+  const float inv_aR = (float)(1.0 / aR);
   const float* src = sino + ((size_t)b * P.n_theta + j) * ns;
-  // samples in order of increasing tau: position i holds sample k = wrap ? ns - 1 - i : i
-  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-    const int k = wrap ? ns - 1 - i : i;
-    gs[i] = src[k];
+  for (int q = threadIdx.x; q < nr; q += blockDim.x) acc[q] = 0.0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+    const float g = src[k] * inv_aR;
     double s = -1.0 + k * P.ds;
     if (wrap) s = -s;
     const double tau = (log(aR * s + (1.0 - aR) * cth) - P.rho0) / P.d_rho;
     const double ft = floor(tau);
-    kqs[i] = min(max((int)ft, -1), nr);
-    als[i] = (float)(tau - ft);
-  }
-  for (int q = threadIdx.x; q < nr; q += blockDim.x) kfirst[q] = ns;
-  __syncthreads();
-  // kfirst[q] = first i with kq_i >= q - 2: sample i is the first for q in (kq_{i-1} + 2, kq_i + 2]
-  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-    const int lo = i == 0 ? 0 : max(kqs[i - 1] + 3, 0);
-    const int hi = min(kqs[i] + 2, nr - 1);
-    for (int q = lo; q <= hi; ++q) kfirst[q] = i;
-  }
-  __syncthreads();
-  const float inv_aR = (float)(1.0 / aR);
-  for (int q = threadIdx.x; q < nr; q += blockDim.x) {
-    float acc = 0.f;
-    for (int i = kfirst[q]; i < ns; ++i) {
-      const int a = q - (kqs[i] - 1);  // tap index of q for sample i; a <= 3 from kfirst
-      if (a < 0) break;
-      acc += bspline_w1(a, als[i]) * gs[i];
-    }
-    xs[q] = acc * inv_aR;
-  }
-  __syncthreads();
-  // taps beyond either end of the row wrap around (only samples with kq <= 0 or kq >= nr - 2)
-  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-    const int kq = kqs[i];
-    if (kq > 0 && kq < nr - 2) continue;
+    const int kq = min(max((int)ft, -1), nr);
+    float w[4];
+    bspline_w((float)(tau - ft), w);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int t = kq - 1 + a;
-      if (t < 0 || t >= nr) atomicAdd(&xs[wrap1(t, nr)], bspline_w1(a, als[i]) * gs[i] * inv_aR);
-    }
+    for (int a = 0; a < 4; ++a) atomicAdd(&acc[wrap1(kq - 1 + a, nr)], (double)(w[a] * g));
   }
   __syncthreads();
+  // FP64 -> FP32 in place: every thread reads its entries before any is overwritten
+  constexpr int kPer = 2 * kRowVals;  // n_rho <= kPer * blockDim.x (checked at plan time)
+  float v[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int q = threadIdx.x + i * blockDim.x;
+    v[i] = q < nr ? (float)acc[q] : 0.f;
+  }
+  __syncthreads();
+  float* xs = reinterpret_cast<float*>(acc);
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int q = threadIdx.x + i * blockDim.x;
+    if (q < nr) xs[q] = v[i];
+  }
+  __syncthreads();
+  float2* sh = reinterpret_cast<float2*>(acc);
   fft_lds<kRowVals, false>(sh, nc, 1, P.tw, P.tw_len);
   rfft_post(sh, nc, P.tw, P.tw_len, [&](int k, float2 x) { dst[k] = x; });
 }
 
 rl_status launch_splat_rfft(const rl_plan* p, const float* sino, float2* spec, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
-  const size_t lds = d.nc * sizeof(float2) + (size_t)d.n_s * 3 * sizeof(float);
+  const size_t lds = (size_t)d.n_rho * sizeof(double);
   dim3 grid(d.n_own, batch * d.m);
   if (lds > 65536) {
     rl_status st = check_hip(hipFuncSetAttribute((const void*)k_splat_rfft, hipFuncAttributeMaxDynamicSharedMemorySize,
