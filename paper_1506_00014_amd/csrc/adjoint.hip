@@ -49,22 +49,17 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
     return;
   }
   const int j = jw & ((1 << 30) - 1);
-  const bool wrap = (jw >> 30) & 1;
-  const double cth = P.own_cos[m * P.n_own + o];
-  const double aR = P.a_R;
-  const float inv_aR = (float)(1.0 / aR);
+  const float inv_aR = (float)(1.0 / P.a_R);
   const float* src = sino + ((size_t)b * P.n_theta + j) * ns;
+  const int2* tr = P.tau + ((size_t)m * P.n_own + o) * ns;  // rho position of each sample
   for (int q = threadIdx.x; q < nr; q += blockDim.x) acc[q] = 0.0;
   __syncthreads();
   for (int k = threadIdx.x; k < ns; k += blockDim.x) {
     const float g = src[k] * inv_aR;
-    double s = -1.0 + k * P.ds;
-    if (wrap) s = -s;
-    const double tau = (log(aR * s + (1.0 - aR) * cth) - P.rho0) / P.d_rho;
-    const double ft = floor(tau);
-    const int kq = min(max((int)ft, -1), nr);
+    const int2 t = tr[k];
+    const int kq = t.x;
     float w[4];
-    bspline_w((float)(tau - ft), w);
+    bspline_w(__int_as_float(t.y), w);
 #pragma unroll
     for (int a = 0; a < 4; ++a) atomicAdd(&acc[wrap1(kq - 1 + a, nr)], (double)(w[a] * g));
   }

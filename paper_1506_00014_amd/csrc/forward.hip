@@ -471,25 +471,20 @@ __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2
   const int jw = P.own_j[m * P.n_own + o];
   if (jw < 0) return;  // uniform across the block
   const int j = jw & ((1 << 30) - 1);
-  const bool wrap = (jw >> 30) & 1;
   const int nc = P.nc, nr = P.n_rho;
   const float2* src = spec + ((size_t)bm * P.n_own + o) * P.ld;
   irfft_pre(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
   __syncthreads();
   fft_lds<kRowVals, true>(sh, nc, 1, P.tw, P.tw_len);
   const float* x = reinterpret_cast<const float*>(sh);
-  const double cth = P.own_cos[m * P.n_own + o];
-  const double aR = P.a_R;
-  const float inv_aR = (float)(1.0 / aR);
+  const float inv_aR = (float)(1.0 / P.a_R);
   float* dst = sino + ((size_t)b * P.n_theta + j) * P.n_s;
+  const int2* tr = P.tau + ((size_t)m * P.n_own + o) * P.n_s;  // rho position of each sample
   for (int k = threadIdx.x; k < P.n_s; k += blockDim.x) {
-    double s = -1.0 + k * P.ds;
-    if (wrap) s = -s;
-    const double tau = (log(aR * s + (1.0 - aR) * cth) - P.rho0) / P.d_rho;
-    const double ft = floor(tau);
+    const int2 t = tr[k];
     float w[4];
-    bspline_w((float)(tau - ft), w);
-    const int kq = min(max((int)ft, -1), nr);
+    bspline_w(__int_as_float(t.y), w);
+    const int kq = t.x;
     float acc = 0.f;
 #pragma unroll
     for (int a = 0; a < 4; ++a) acc += w[a] * x[wrap1(kq - 1 + a, nr)];

@@ -181,6 +181,31 @@ rl_status validate(const rl_geom& g) {
   return RL_OK;
 }
 
+// rho position of every sample of every owned sinogram row (eq. Sm_def): tau = (log(a_R s +
+// (1 - a_R) cos theta') - rho_0) / d_rho, s -> -s on the wrapped rows.  Stored as floor(tau)
+// (clamped to [-1, n_rho]) and the FP32 fraction, which the 4-tap evaluation and its
+// transpose read instead of recomputing the logarithm.
+__global__ __launch_bounds__(256) void k_tau_table(DevPlan P, int2* __restrict__ tab) {
+  const int o = blockIdx.x, m = blockIdx.y;
+  const int jw = P.own_j[m * P.n_own + o];
+  int2* row = tab + ((size_t)m * P.n_own + o) * P.n_s;
+  if (jw < 0) {
+    for (int k = threadIdx.x; k < P.n_s; k += blockDim.x) row[k] = make_int2(0, 0);
+    return;
+  }
+  const bool wrap = (jw >> 30) & 1;
+  const double cth = P.own_cos[m * P.n_own + o];
+  const double aR = P.a_R;
+  for (int k = threadIdx.x; k < P.n_s; k += blockDim.x) {
+    double s = -1.0 + k * P.ds;
+    if (wrap) s = -s;
+    const double tau = (log(aR * s + (1.0 - aR) * cth) - P.rho0) / P.d_rho;
+    const double ft = floor(tau);
+    const int kq = (int)fmin(fmax(ft, -1.0), (double)P.n_rho);
+    row[k] = make_int2(kq, __float_as_int((float)(tau - ft)));
+  }
+}
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -459,6 +484,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   const size_t o_pf = off; off += al(sizeof(float) * pref.size());
   const size_t o_er = off; off += al(sizeof(double) * erho.size());
   const size_t o_dt = off; off += al(sizeof(float) * dtap.size());
+  const size_t o_ta = off; off += al(sizeof(int2) * (size_t)M * n_own * g.n_s);
   const size_t table_bytes = off;
   // scratch for the quadrature (freed before returning)
   const size_t s_u = 0, s_a = al(sizeof(double) * n_nodes_pad), s_l = 2 * s_a, s_z = 3 * s_a;
@@ -542,6 +568,10 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   d.pref = (const float*)(mem + o_pf);
   d.erho = (const double*)(mem + o_er);
   d.dtap = (const float*)(mem + o_dt);
+  d.tau = (const int2*)(mem + o_ta);
+  hipLaunchKernelGGL(k_tau_table, dim3(n_own, M), dim3(256), 0, 0, d, (int2*)(mem + o_ta));
+  if ((st = check_launch("k_tau_table")) != RL_OK) return cleanup(st);
+  if ((st = check_hip(hipDeviceSynchronize(), "k_tau_table")) != RL_OK) return cleanup(st);
   plan->d_mem = mem;
   plan->d_mem_bytes = table_bytes;
   cleanup(RL_OK);

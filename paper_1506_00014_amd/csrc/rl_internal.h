@@ -37,6 +37,8 @@ struct DevPlan {
   const float* ramp;       // [lr/2 + 1] ramp multiplier (real), includes 1/lr
   const float* pref;       // [kPrefR + 1] prefilter taps sqrt(3) z^|k|
   const double* erho;      // [n_rho] e^{rho_q} / (a_R dx): image-index length of the ray at rho_q
+  const int2* tau;         // [m][n_own][n_s] rho position tau of S_m(theta_j, s_k) on each owned
+                           // row: (floor(tau) clamped to [-1, n_rho], bits of the FP32 fraction)
   const float* dtap;       // [4r - 1] decimation taps d_n, n = -(2r-1) .. 2r-1
 };
 
