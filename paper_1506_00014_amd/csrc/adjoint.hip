@@ -290,30 +290,34 @@ __device__ __forceinline__ void splat_walk(const SegWalk& sw, double* acc, const
   }
 }
 
-__global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const float* __restrict__ U,
-                                                              float* __restrict__ cbar) {
-  // FP64: LDS float atomics are slow on this target.
-  __shared__ double acc[kAW * kAP];
-  // per ray slot (slot of ray k of a pass: (k % kRayGap) * ng + k / kRayGap)
+// ---- splat passes, built once per plan
+// A pass is one partition m, one periodic shift (sx, sy) of one tile and up to kARows fine
+// rays ta .. ta + nrows - 1, laid out in ray slots (slot of ray k: (k % kRayGap) * ng +
+// k / kRayGap, ng = ceil(nrows / kRayGap); slots past the last ray are empty).  Header, three
+// int4: (m, sx, sy, nslot), (cg0, cg1, qlo, qhi), (seglen, segments, first slot record, 0);
+// one int4 per slot: (t, first rho index, last rho index, first segment).  The kernel below
+// computes them (one block per tile): COUNT only counts passes and slots per tile, WRITE
+// stores them at the offsets the host derives from the counts.
+constexpr int kBThreads = 256;  // threads of the pass builder (>= kASlots)
+
+template <bool WRITE>
+__global__ __launch_bounds__(kBThreads) void k_adj_build(DevPlan P, int2* __restrict__ counts,
+                                                         const int2* __restrict__ offs, int4* __restrict__ passes,
+                                                         int4* __restrict__ rays) {
   __shared__ int rq0[kASlots];
+  __shared__ int rqb[kASlots];
   __shared__ int rpre[kASlots + 1];
-  __shared__ int rcnt[kASlots];
-  __shared__ int rcg[kASlots];
-  __shared__ float4 rdw[kASlots];
-  __shared__ double2 rcs[kASlots];
-  __shared__ float us[kUCap];   // coarse rows [cg0, cg0 + nur) x rho indices [qlo, qlo + span)
-  __shared__ double es[kECap];  // e^{rho_q} / (a_R dx) for q in [qlo, qlo + span)
-  __shared__ int qext[3];  // rho range of the pass; segment length
+  __shared__ int qext[3];
   const int n = P.n, r = P.r;
+  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
-  const int b = blockIdx.z;
-  for (int i = threadIdx.x; i < kAW * kAP; i += blockDim.x) acc[i] = 0.0;
   const int txe = min(tx0 + kTile, n), tye = min(ty0 + kTile, n);
+  int npass = 0, nrec = 0;
+  const int pass0 = WRITE ? offs[tile].x : 0, rec0 = WRITE ? offs[tile].y : 0;
   for (int m = 0; m < P.m; ++m) {
     const double cb = cos(m * P.beta), sb = sin(m * P.beta);
     const double2* cs = P.fine_cs + (size_t)m * P.n_fine;
     const int2* fq = P.fine_q + (size_t)m * P.n_fine;
-    const float* Ub = U + (size_t)(b * P.m + m) * P.n_sup * P.n_rho;
     const double X0 = P.X0[m], Y0 = P.Y0[m];
     for (int sy = -1; sy <= 1; ++sy) {
       for (int sx = -1; sx <= 1; ++sx) {
@@ -329,14 +333,13 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
           const double ex = fmax(fmax(x1a, -x1b), 0.0), ey = fmax(fmax(x2a, -x2b), 0.0);
           if (ex * ex + ey * ey >= 1.0) continue;  // rectangle misses the unit disc
         }
-        // angular extent of the rectangle seen from x* (which lies outside it); FP32 is ample:
-        // the ray range below is padded by one fine ray (~1e-4 rad or more)
-        float phmin = 1e30f, phmax = -1e30f;
+        // angular extent of the rectangle seen from x* (which lies outside it), padded by a ray
+        double phmin = 1e30, phmax = -1e30;
         for (int c = 0; c < 4; ++c) {
           const double dX = ((c & 1) ? Xb : Xa) - X0, dY = ((c & 2) ? Yb : Ya) - Y0;
-          const float ph = atan2f((float)(-sb * dX + cb * dY), (float)(cb * dX + sb * dY));
-          phmin = fminf(phmin, ph);
-          phmax = fmaxf(phmax, ph);
+          const double ph = atan2(-sb * dX + cb * dY, cb * dX + sb * dY);
+          phmin = fmin(phmin, ph);
+          phmax = fmax(phmax, ph);
         }
         const double fstep = P.dtheta / r;
         const int ta = max(P.t_min, (int)floor((phmin - P.phi0[m]) / fstep) - 1);
@@ -350,19 +353,14 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
             qext[1] = -0x7fffffff;
           }
           __syncthreads();
-          // 1) rho range of each ray inside the grown tile (slab test) and inside D
+          // rho range of each ray inside the grown tile (slab test) and inside D
           for (int sl = threadIdx.x; sl < nslot; sl += blockDim.x) {
             const int k = (sl % ng) * kRayGap + sl / ng;  // ray of slot sl
             int qa = 0, qb = -1;
             if (k < nrows) {
-              const int t = tc + k;
-              const int ti = t - P.t_min;
+              const int ti = tc + k - P.t_min;
               const int2 qr = fq[ti];
               const double2 tcs = cs[ti];
-              const int cg = floordiv(t, r);
-              rcg[sl] = cg;
-              rdw[sl] = P.dec[t - r * cg];
-              rcs[sl] = tcs;
               if (qr.x <= qr.y) {
                 double elo = 0.0, ehi = 1e300;
                 bool ok = true;
@@ -385,7 +383,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
                 // (within D, X and Y lie in (0, n), so the clip to [0, n] changes nothing):
                 // E in [elo, ehi], rho indices from ceil(tau(elo)) to floor(tau(ehi)).  Rounding
                 // can only misplace a sample within ~1e-9 pixel of a footprint edge, where its
-                // weight on the tile is zero; the halo holds such a footprint
+                // weight on the tile is zero; the tile's halo holds such a footprint
                 if (ok && elo <= ehi && ehi > 0.0) {
                   const double scale = P.a_R * P.dx;
                   const double tlo = log(fmax(elo * scale, 1e-300)) / P.d_rho + P.n_rho - 1;
@@ -401,12 +399,12 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
               atomicMax(&qext[1], qb);
             }
             rq0[sl] = qa;
-            rcnt[sl] = qb;
+            rqb[sl] = qb;
             rpre[sl] = cnt;
           }
           __syncthreads();
-          // segment length: long enough that every thread walks at most one segment
-          // (sum over rays of ceil(cnt / len) <= samples / len + rays <= blockDim.x)
+          // segment length: long enough that every thread of the splat walks at most one
+          // segment (sum over rays of ceil(cnt / len) <= samples / len + rays <= kAThreads)
           if (threadIdx.x < 64) {
             int ssum = 0, nray = 0;
             for (int i = threadIdx.x; i < nslot; i += 64) {
@@ -427,86 +425,214 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
             }
           }
           __syncthreads();
-          const int total = rpre[nslot], seglen = qext[2];
-          if (total == 0) continue;  // uniform; the loop head synchronises before the next pass
-          // 2) rho windows: the coarse rows cg - 1 .. cg + 2 of the pass's rays and e^rho are
-          //    copied to LDS (coalesced rows, all loads of a thread issued together) for one
-          //    window of rho indices at a time; one window usually covers the whole pass
-          const int qlo = qext[0], qhi = qext[1];
-          const int cg0 = max(floordiv(tc, r) - 1, 0);
-          const int cg1 = min(floordiv(tc + nrows - 1, r) + 2, P.n_sup - 1);
-          const int nur = cg1 - cg0 + 1;
-          const int wlen = min(kECap, kUCap / nur);
-          for (int wq = qlo; wq <= qhi; wq += wlen) {
-            const int span = min(wlen, qhi - wq + 1);
-            {
-              constexpr int kIt = (kUCap + kAThreads - 1) / kAThreads;
-              const int tot = nur * span;
-              // element i = threadIdx.x + it * kAThreads is (row, qq) = divmod(i, span); both
-              // advance by the block stride without a division per element
-              const int drow = kAThreads / span, dqq = kAThreads - drow * span;
-              int row = (int)threadIdx.x / span, qq = (int)threadIdx.x - row * span;
-              float tmp[kIt];
-#pragma unroll
-              for (int it = 0; it < kIt; ++it) {
-                const int i = threadIdx.x + it * kAThreads;
-                tmp[it] = i < tot ? Ub[(size_t)(cg0 + row) * P.n_rho + wq + qq] : 0.f;
-                row += drow;
-                qq += dqq;
-                if (qq >= span) {
-                  qq -= span;
-                  ++row;
-                }
+          const int total = rpre[nslot];
+          if (total > 0) {  // uniform
+            if (WRITE) {
+              const int cg0 = max(floordiv(tc, r) - 1, 0);
+              const int cg1 = min(floordiv(tc + nrows - 1, r) + 2, P.n_sup - 1);
+              if (threadIdx.x == 0) {
+                int4* h = passes + 3 * (size_t)(pass0 + npass);
+                h[0] = make_int4(m, sx, sy, nslot);
+                h[1] = make_int4(cg0, cg1, qext[0], qext[1]);
+                h[2] = make_int4(qext[2], total, rec0 + nrec, 0);
               }
-              const double e = threadIdx.x < span ? P.erho[wq + threadIdx.x] : 0.0;
-#pragma unroll
-              for (int it = 0; it < kIt; ++it) {
-                const int i = threadIdx.x + it * kAThreads;
-                if (i < tot) us[i] = tmp[it];
+              for (int sl = threadIdx.x; sl < nslot; sl += blockDim.x) {
+                const int k = (sl % ng) * kRayGap + sl / ng;
+                rays[rec0 + nrec + sl] = make_int4(tc + min(k, nrows - 1), rq0[sl], rqb[sl], rpre[sl]);
               }
-              if (threadIdx.x < span) es[threadIdx.x] = e;
             }
-            __syncthreads();
-            // 3) walk whole segments (clipped to the window)
-            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-              // the slot holding segment idx: the last k with rpre[k] <= idx
-              int lo = 0, hi = nslot - 1;
-              while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (rpre[mid] <= idx) lo = mid;
-                else hi = mid - 1;
-              }
-              const int k = lo;
-              SegWalk sw;
-              sw.X0 = X0;
-              sw.Y0 = Y0;
-              const double2 tcs = rcs[k];
-              sw.cx = tcs.x;
-              sw.cy = tcs.y;
-              const int q0 = rq0[k] + (idx - rpre[k]) * seglen;
-              sw.qbeg = max(q0, wq);
-              sw.qend = min(min(q0 + seglen - 1, rcnt[k]), wq + span - 1);
-              sw.ux0 = ux0;
-              sw.ux1 = ux1;
-              sw.uy0 = uy0;
-              sw.uy1 = uy1;
-              const int cg = rcg[k];
-              const float4 dw = rdw[k];
-              const float dwv[4] = {dw.x, dw.y, dw.z, dw.w};
-              // coarse rows cg-1 .. cg+2 feed this ray; a row outside the support gets weight 0
-              // and reads a copied row instead
+            ++npass;
+            nrec += nslot;
+          }
+          __syncthreads();
+        }
+      }
+    }
+  }
+  if (!WRITE && threadIdx.x == 0) counts[tile] = make_int2(npass, nrec);
+}
+
+rl_status build_adj_passes(rl_plan* p) {
+  DevPlan& d = p->d;
+  const int nt = (d.n + kTile - 1) / kTile;
+  const int tiles = nt * nt;
+  int2* dcnt = nullptr;
+  rl_status st;
+  if ((st = check_hip(hipMalloc(&dcnt, sizeof(int2) * tiles), "hipMalloc(pass counts)")) != RL_OK) return st;
+  hipLaunchKernelGGL(k_adj_build<false>, dim3(nt, nt), dim3(kBThreads), 0, 0, d, dcnt, nullptr, nullptr, nullptr);
+  std::vector<int2> cnt(tiles);
+  if ((st = check_launch("k_adj_build")) != RL_OK ||
+      (st = check_hip(hipMemcpy(cnt.data(), dcnt, sizeof(int2) * tiles, hipMemcpyDeviceToHost), "copy pass counts")) !=
+          RL_OK) {
+    (void)hipFree(dcnt);
+    return st;
+  }
+  // offsets: tile t's passes start at offs[t].x, its slot records at offs[t].y
+  std::vector<int2> offs(tiles);
+  std::vector<int> toff(tiles + 1);
+  long long np = 0, nr = 0;
+  for (int t = 0; t < tiles; ++t) {
+    offs[t] = make_int2((int)np, (int)nr);
+    toff[t] = (int)np;
+    np += cnt[t].x;
+    nr += cnt[t].y;
+  }
+  toff[tiles] = (int)np;
+  if (np >= (1ll << 30) || nr >= (1ll << 30)) {
+    (void)hipFree(dcnt);
+    return fail(RL_ERR_GEOMETRY, "adjoint splat tables too large");
+  }
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t o_off = 0, o_pass = al(sizeof(int) * (tiles + 1)), o_ray = o_pass + al(sizeof(int4) * 3 * (np + 1));
+  const size_t bytes = o_ray + al(sizeof(int4) * (nr + 1)) + al(sizeof(int2) * tiles);
+  const size_t o_offs = bytes - al(sizeof(int2) * tiles);
+  char* mem = nullptr;
+  if ((st = check_hip(hipMalloc(&mem, bytes), "hipMalloc(adjoint passes)")) != RL_OK) {
+    (void)hipFree(dcnt);
+    return st;
+  }
+  (void)hipFree(dcnt);
+  if ((st = check_hip(hipMemcpy(mem + o_off, toff.data(), sizeof(int) * (tiles + 1), hipMemcpyHostToDevice),
+                      "upload pass offsets")) != RL_OK ||
+      (st = check_hip(hipMemcpy(mem + o_offs, offs.data(), sizeof(int2) * tiles, hipMemcpyHostToDevice),
+                      "upload pass offsets")) != RL_OK) {
+    (void)hipFree(mem);
+    return st;
+  }
+  hipLaunchKernelGGL(k_adj_build<true>, dim3(nt, nt), dim3(kBThreads), 0, 0, d, nullptr, (const int2*)(mem + o_offs),
+                     (int4*)(mem + o_pass), (int4*)(mem + o_ray));
+  if ((st = check_launch("k_adj_build")) != RL_OK ||
+      (st = check_hip(hipDeviceSynchronize(), "k_adj_build")) != RL_OK) {
+    (void)hipFree(mem);
+    return st;
+  }
+  d.adj_ntx = nt;
+  d.adj_off = (const int*)(mem + o_off);
+  d.adj_pass = (const int4*)(mem + o_pass);
+  d.adj_ray = (const int4*)(mem + o_ray);
+  p->d_adj = mem;
+  p->d_adj_bytes = bytes;
+  return RL_OK;
+}
+
+// ---- the splat
+// Block: one kTile x kTile image tile of one slice.  For every pass of the tile (built at
+// plan time, above), the pass's ray slots are read into LDS, the coarse rows cg - 1 .. cg + 2
+// of its rays are copied to LDS with e^rho for one window of rho indices at a time (one
+// window usually covers the pass), and every thread walks at most one segment.  The FP64
+// tile (with its halo) collects all partitions and is written once.
+__global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const float* __restrict__ U,
+                                                              float* __restrict__ cbar) {
+  // FP64: LDS float atomics are slow on this target.
+  __shared__ double acc[kAW * kAP];
+  __shared__ int rq0[kASlots];
+  __shared__ int rpre[kASlots + 1];
+  __shared__ int rcnt[kASlots];
+  __shared__ int rcg[kASlots];
+  __shared__ float4 rdw[kASlots];
+  __shared__ double2 rcs[kASlots];
+  __shared__ float us[kUCap];   // coarse rows [cg0, cg0 + nur) x rho indices [wq, wq + span)
+  __shared__ double es[kECap];  // e^{rho_q} / (a_R dx) for q in [wq, wq + span)
+  const int n = P.n, r = P.r;
+  const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
+  const int b = blockIdx.z;
+  const int tile = blockIdx.y * P.adj_ntx + blockIdx.x;
+  for (int i = threadIdx.x; i < kAW * kAP; i += blockDim.x) acc[i] = 0.0;
+  const int txe = min(tx0 + kTile, n), tye = min(ty0 + kTile, n);
+  const int pbeg = P.adj_off[tile], pend = P.adj_off[tile + 1];
+  for (int pi = pbeg; pi < pend; ++pi) {
+    const int4 h0 = P.adj_pass[3 * pi], h1 = P.adj_pass[3 * pi + 1], h2 = P.adj_pass[3 * pi + 2];
+    const int m = h0.x, nslot = h0.w;
+    const int ux0 = tx0 + h0.y * n, ux1 = txe + h0.y * n;
+    const int uy0 = ty0 + h0.z * n, uy1 = tye + h0.z * n;
+    const int cg0 = h1.x, cg1 = h1.y, qlo = h1.z, qhi = h1.w;
+    const int seglen = h2.x, total = h2.y;
+    const int4* rec = P.adj_ray + h2.z;
+    const double2* cs = P.fine_cs + (size_t)m * P.n_fine;
+    const float* Ub = U + (size_t)(b * P.m + m) * P.n_sup * P.n_rho;
+    const double X0 = P.X0[m], Y0 = P.Y0[m];
+    __syncthreads();  // the previous pass's walk is done with the LDS slots
+    for (int sl = threadIdx.x; sl < nslot; sl += blockDim.x) {
+      const int4 e = rec[sl];
+      const int cg = floordiv(e.x, r);
+      rq0[sl] = e.y;
+      rcnt[sl] = e.z;
+      rpre[sl] = e.w;
+      rcs[sl] = cs[e.x - P.t_min];
+      rcg[sl] = cg;
+      rdw[sl] = P.dec[e.x - r * cg];
+    }
+    if (threadIdx.x == 0) rpre[nslot] = total;
+    // rho windows of the row copies
+    const int nur = cg1 - cg0 + 1;
+    const int wlen = min(kECap, kUCap / nur);
+    for (int wq = qlo; wq <= qhi; wq += wlen) {
+      const int span = min(wlen, qhi - wq + 1);
+      if (wq > qlo) __syncthreads();  // the previous window's walk is done with the copies
+      {
+        constexpr int kIt = (kUCap + kAThreads - 1) / kAThreads;
+        const int tot = nur * span;
+        // element i = threadIdx.x + it * kAThreads is (row, qq) = divmod(i, span); both
+        // advance by the block stride without a division per element
+        const int drow = kAThreads / span, dqq = kAThreads - drow * span;
+        int row = (int)threadIdx.x / span, qq = (int)threadIdx.x - row * span;
+        float tmp[kIt];
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const int row = cg - 1 + i;
-                const bool ok = row >= 0 && row < P.n_sup;
-                sw.dw[i] = ok ? dwv[i] : 0.f;
-                sw.roff[i] = (min(max(row, cg0), cg1) - cg0) * span;
-              }
-              splat_walk(sw, acc, us, es, wq);
-            }
-            __syncthreads();
+        for (int it = 0; it < kIt; ++it) {
+          const int i = threadIdx.x + it * kAThreads;
+          tmp[it] = i < tot ? Ub[(size_t)(cg0 + row) * P.n_rho + wq + qq] : 0.f;
+          row += drow;
+          qq += dqq;
+          if (qq >= span) {
+            qq -= span;
+            ++row;
           }
         }
+        const double e = threadIdx.x < span ? P.erho[wq + threadIdx.x] : 0.0;
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+          const int i = threadIdx.x + it * kAThreads;
+          if (i < tot) us[i] = tmp[it];
+        }
+        if (threadIdx.x < span) es[threadIdx.x] = e;
+      }
+      __syncthreads();
+      // walk whole segments (clipped to the window)
+      for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        // the slot holding segment idx: the last k with rpre[k] <= idx
+        int lo = 0, hi = nslot - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (rpre[mid] <= idx) lo = mid;
+          else hi = mid - 1;
+        }
+        const int k = lo;
+        SegWalk sw;
+        sw.X0 = X0;
+        sw.Y0 = Y0;
+        const double2 tcs = rcs[k];
+        sw.cx = tcs.x;
+        sw.cy = tcs.y;
+        const int q0 = rq0[k] + (idx - rpre[k]) * seglen;
+        sw.qbeg = max(q0, wq);
+        sw.qend = min(min(q0 + seglen - 1, rcnt[k]), wq + span - 1);
+        sw.ux0 = ux0;
+        sw.ux1 = ux1;
+        sw.uy0 = uy0;
+        sw.uy1 = uy1;
+        const int cg = rcg[k];
+        const float4 dw = rdw[k];
+        const float dwv[4] = {dw.x, dw.y, dw.z, dw.w};
+        // coarse rows cg-1 .. cg+2 feed this ray; a row outside the support gets weight 0
+        // and reads a copied row instead
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = cg - 1 + i;
+          const bool ok = row >= 0 && row < P.n_sup;
+          sw.dw[i] = ok ? dwv[i] : 0.f;
+          sw.roff[i] = (min(max(row, cg0), cg1) - cg0) * span;
+        }
+        splat_walk(sw, acc, us, es, wq);
       }
     }
   }

@@ -574,6 +574,12 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   if ((st = check_hip(hipDeviceSynchronize(), "k_tau_table")) != RL_OK) return cleanup(st);
   plan->d_mem = mem;
   plan->d_mem_bytes = table_bytes;
+  plan->d_adj = nullptr;
+  plan->d_adj_bytes = 0;
+  if ((st = build_adj_passes(plan)) != RL_OK) {
+    plan->d_mem = nullptr;  // freed by cleanup
+    return cleanup(st);
+  }
   cleanup(RL_OK);
   *out = plan;
   return RL_OK;
@@ -582,6 +588,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
 extern "C" void rl_plan_destroy(rl_plan* plan) {
   if (!plan) return;
   if (plan->d_mem) (void)hipFree(plan->d_mem);
+  if (plan->d_adj) (void)hipFree(plan->d_adj);
   delete plan;
 }
 

@@ -40,6 +40,11 @@ struct DevPlan {
   const int2* tau;         // [m][n_own][n_s] rho position tau of S_m(theta_j, s_k) on each owned
                            // row: (floor(tau) clamped to [-1, n_rho], bits of the FP32 fraction)
   const float* dtap;       // [4r - 1] decimation taps d_n, n = -(2r-1) .. 2r-1
+  // splat passes of the adjoint (geometry only, built at plan time), see adjoint.hip
+  int adj_ntx;             // tiles per image row
+  const int* adj_off;      // [tiles + 1] first pass of each tile
+  const int4* adj_pass;    // [passes][3] header of each pass
+  const int4* adj_ray;     // [ray slots] (t, first rho, last rho, first segment) per slot
 };
 
 }  // namespace rl
@@ -51,6 +56,8 @@ struct rl_plan {
   std::vector<int> rows_per_part;
   void* d_mem;  // single device allocation holding all tables
   size_t d_mem_bytes;
+  void* d_adj;  // device allocation holding the adjoint splat passes
+  size_t d_adj_bytes;
 };
 
 namespace rl {
@@ -98,5 +105,7 @@ rl_status launch_lp2cart_adj(const rl_plan* p, const float* u, float* cbar, int 
 rl_status launch_ramp(const rl_plan* p, const float* in, float* out, int batch, hipStream_t s);
 rl_status launch_irfft_rows(const rl_plan* p, const float2* spec, float* out, int rows,
                             hipStream_t s);
+// Plan time: build the adjoint splat passes (allocates plan->d_adj, fills the adj_* fields).
+rl_status build_adj_passes(rl_plan* p);
 
 }  // namespace rl
