@@ -246,4 +246,15 @@ __device__ __forceinline__ void bspline_w(float a, float* w) {
 
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Blocks are dispatched to the chip's 8 XCDs (each with its own L2) round-robin by linear
+// block id.  xcd_block maps a linear id to a logical block such that every XCD gets one
+// contiguous run of logical blocks: neighbouring blocks, which share cache lines, then run
+// on the same XCD, one after the other.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int id, int nblocks) {
+  const int xcd = id % kXcds, local = id / kXcds;
+  const int per = nblocks / kXcds, rem = nblocks % kXcds;
+  return xcd * per + min(xcd, rem) + local;
+}
+
 }  // namespace rl

@@ -349,8 +349,10 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
   constexpr int RS = K2 + 1;           // padded stride between k1 rows
   constexpr int CS = K1 * RS + 1;      // padded stride between columns
   const int nkt = K / 2 + 1, ncol = P.nc + 1;
-  const int bm = blockIdx.y;
-  const int col0 = blockIdx.x * cw;
+  // neighbouring column strips share 128-byte lines: keep them on one XCD
+  const int lid = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bm = lid / gridDim.x;
+  const int col0 = (lid - bm * gridDim.x) * cw;
   const int tw_step = P.tw_len / K;
   const float2* src = in + (size_t)bm * in_rows * P.ld;
   // stage A
