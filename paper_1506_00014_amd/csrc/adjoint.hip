@@ -19,15 +19,6 @@
 
 namespace rl {
 
-__device__ __forceinline__ float bspline_w1(int a, float al) {
-  const float a2 = al * al, a3 = a2 * al, b = 1.0f - al;
-  float w = b * b * b;
-  w = (a == 1) ? (3.0f * a3 - 6.0f * a2 + 4.0f) : w;
-  w = (a == 2) ? (-3.0f * a3 + 3.0f * a2 + 3.0f * al + 1.0f) : w;
-  w = (a == 3) ? a3 : w;
-  return w * (1.0f / 6.0f);
-}
-
 // ------------------------------------------------------------------ transpose of step 7
 // One owned row per block.  The forward evaluation reads, for every sinogram sample k, the
 // four periodic taps kq_k - 1 .. kq_k + 2 (kq_k = floor(tau_k)) of the log-polar row; its
@@ -49,7 +40,7 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
     return;
   }
   const int j = jw & ((1 << 30) - 1);
-  const float inv_aR = (float)(1.0 / P.a_R);
+  const float inv_aR = (float)(1.0 / (6.0 * P.a_R));  // 1/a_R and the weights' 1/6
   const float* src = sino + ((size_t)b * P.n_theta + j) * ns;
   const int2* tr = P.tau + ((size_t)m * P.n_own + o) * ns;  // rho position of each sample
   for (int q = threadIdx.x; q < nr; q += blockDim.x) acc[q] = 0.0;
@@ -59,7 +50,7 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
     const int2 t = tr[k];
     const int kq = t.x;
     float w[4];
-    bspline_w(__int_as_float(t.y), w);
+    bspline_w6(__int_as_float(t.y), w);
 #pragma unroll
     for (int a = 0; a < 4; ++a) atomicAdd(&acc[wrap1(kq - 1 + a, nr)], (double)(w[a] * g));
   }
@@ -219,6 +210,7 @@ __device__ __forceinline__ void splat_walk(const SegWalk& sw, double* acc, const
   for (int q = sw.qbeg; q <= sw.qend; ++q) {
     const int qi = q - qlo;
     const double E = erho[qi];
+    // (dw carries the weights' 1/36)
     const float V = sw.dw[0] * rows[sw.roff[0] + qi] + sw.dw[1] * rows[sw.roff[1] + qi] +
                     sw.dw[2] * rows[sw.roff[2] + qi] + sw.dw[3] * rows[sw.roff[3] + qi];
     const double X = sw.X0 + E * sw.cx, Y = sw.Y0 + E * sw.cy;
@@ -272,8 +264,8 @@ __device__ __forceinline__ void splat_walk(const SegWalk& sw, double* acc, const
     }
     const float ax = (float)(X - fx), ay = (float)(Y - fy);
     float wx[4], wy[4];
-    bspline_w(xp ? ax : 1.0f - ax, wx);
-    bspline_w(yp ? ay : 1.0f - ay, wy);
+    bspline_w6(xp ? ax : 1.0f - ax, wx);
+    bspline_w6(yp ? ay : 1.0f - ay, wy);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float vy = V * wy[j];
@@ -629,7 +621,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
         for (int i = 0; i < 4; ++i) {
           const int row = cg - 1 + i;
           const bool ok = row >= 0 && row < P.n_sup;
-          sw.dw[i] = ok ? dwv[i] : 0.f;
+          sw.dw[i] = ok ? dwv[i] * (1.0f / 36.0f) : 0.f;
           sw.roff[i] = (min(max(row, cg0), cg1) - cg0) * span;
         }
         splat_walk(sw, acc, us, es, wq);

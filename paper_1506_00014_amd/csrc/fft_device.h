@@ -234,14 +234,15 @@ __device__ __forceinline__ void reg_fft(float2 (&v)[R], const float2* __restrict
   }
 }
 
-// Cubic B-spline weights for taps k-1, k, k+1, k+2 at fractional offset a in [0, 1).
-__device__ __forceinline__ void bspline_w(float a, float* w) {
+// Six times the cubic B-spline weights for taps k-1, k, k+1, k+2 at fractional offset a in
+// [0, 1) (the factor 1/6 per dimension is applied once to the value instead).
+__device__ __forceinline__ void bspline_w6(float a, float* w) {
   const float a2 = a * a, a3 = a2 * a;
   const float b = 1.0f - a;
-  w[0] = b * b * b * (1.0f / 6.0f);
-  w[1] = (3.0f * a3 - 6.0f * a2 + 4.0f) * (1.0f / 6.0f);
-  w[2] = (-3.0f * a3 + 3.0f * a2 + 3.0f * a + 1.0f) * (1.0f / 6.0f);
-  w[3] = a3 * (1.0f / 6.0f);
+  w[0] = b * b * b;
+  w[1] = fmaf(3.0f, a3, fmaf(-6.0f, a2, 4.0f));
+  w[2] = fmaf(-3.0f, a3, fmaf(3.0f, a2, fmaf(3.0f, a, 1.0f)));
+  w[3] = a3;
 }
 
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }

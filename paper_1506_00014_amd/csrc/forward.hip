@@ -94,8 +94,8 @@ template <class Tap>
 __device__ __forceinline__ float bicubic_at(double X, double Y, int n, Tap tap) {
   const double fx = floor(X), fy = floor(Y);
   float wx[4], wy[4];
-  bspline_w((float)(X - fx), wx);
-  bspline_w((float)(Y - fy), wy);
+  bspline_w6((float)(X - fx), wx);
+  bspline_w6((float)(Y - fy), wy);
   const int kx = min(max((int)fx, -1), n), ky = min(max((int)fy, -1), n);
   float v = 0.f;
 #pragma unroll
@@ -105,7 +105,7 @@ __device__ __forceinline__ float bicubic_at(double X, double Y, int n, Tap tap) 
     for (int a = 0; a < 4; ++a) h += wx[a] * tap(kx - 1 + a, ky - 1 + bb);
     v += wy[bb] * h;
   }
-  return v;
+  return v * (1.0f / 36.0f);
 }
 
 // Block: kFQ consecutive rho indices and kFRows coarse rows of one (slice, partition).
@@ -241,8 +241,8 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
           // the 4 x 4 taps start at (kx - 1, ky - 1); the patch holds them (clamped for safety)
           const double fx = floor(X), fy = floor(Y);
           float wx[4], wy[4];
-          bspline_w((float)(X - fx), wx);
-          bspline_w((float)(Y - fy), wy);
+          bspline_w6((float)(X - fx), wx);
+          bspline_w6((float)(Y - fy), wy);
           const int bx = min(max((int)fx - 1 - Xlo, 0), W - 4);
           const int by = min(max((int)fy - 1 - Ylo, 0), H - 4);
           const float* p0 = patch + by * Wp + bx;
@@ -251,6 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
             const float* pr = p0 + bb * Wp;
             v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
           }
+          v *= 1.0f / 36.0f;
         } else {
           v = bicubic_at(X, Y, n, [&](int x, int y) { return img[(size_t)wrap1(y, n) * n + wrap1(x, n)]; });
         }
@@ -479,13 +480,13 @@ __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2
   __syncthreads();
   fft_lds<kRowVals, true>(sh, nc, 1, P.tw, P.tw_len);
   const float* x = reinterpret_cast<const float*>(sh);
-  const float inv_aR = (float)(1.0 / P.a_R);
+  const float inv_aR = (float)(1.0 / (6.0 * P.a_R));  // 1/a_R and the weights' 1/6
   float* dst = sino + ((size_t)b * P.n_theta + j) * P.n_s;
   const int2* tr = P.tau + ((size_t)m * P.n_own + o) * P.n_s;  // rho position of each sample
   for (int k = threadIdx.x; k < P.n_s; k += blockDim.x) {
     const int2 t = tr[k];
     float w[4];
-    bspline_w(__int_as_float(t.y), w);
+    bspline_w6(__int_as_float(t.y), w);
     const int kq = t.x;
     float acc = 0.f;
 #pragma unroll
