@@ -27,6 +27,11 @@ if ROOT not in sys.path:
 
 METRIC = "slices/s for R and R# at N=2048 fp32, batched vs plain; % of HBM peak"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
+# Algorithmic FP32 operations per fine log-polar sample of the two interpolation kernels:
+# the 4 x 4 tensor-product weights and their sum (4 + 16 products, 16 sums), the eight
+# cubic weights (2 x 10), and the four-tap decimation filter or its transpose (8).
+ALG_FLOPS_PER_SAMPLE = {"k_lp2cart_adj": 64, "k_cart2lp": 64}
 
 
 def kernel_bytes(name, g, n_own, batch):
@@ -255,9 +260,18 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     dk = kernels[dom]
     tr = measured_traffic(dom, B, n)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dk["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": tr["bytes"] if tr else None,
-                "alg_bytes": dk["alg_bytes_per_launch"]}
+    if dom in ALG_FLOPS_PER_SAMPLE:
+        # an interpolation kernel: bound by arithmetic issue, not by HBM (its bytes are in detail)
+        flops = plan.fine_samples() * B * ALG_FLOPS_PER_SAMPLE[dom]
+        achieved = flops / (dk["avg_ms"] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                    "traffic": tr["bytes"] if tr else None, "alg_flops": flops,
+                    "alg_bytes": dk["alg_bytes_per_launch"], "hbm_GBps": dk["alg_GBps"]}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(dk["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": tr["bytes"] if tr else None,
+                    "alg_bytes": dk["alg_bytes_per_launch"]}
     if tr:
         roofline["traffic_detail"] = tr
 

@@ -113,6 +113,12 @@ rl_status rl_plan_geometry(const rl_plan* plan, rl_geom* out);
 /* Workspace bytes needed by one call of `op` on `batch` slices (0 if batch == 0). */
 size_t rl_workspace_bytes(const rl_plan* plan, int32_t batch, rl_op op);
 
+/* Number of fine log-polar samples inside D of one slice, summed over the M partitions
+ * (sec. 4, eq. Lopolargrid_f and circle_D): the bicubic interpolations one R or R# performs
+ * per slice, for work accounting.  Host-side, from the plan's tables.  Writes *out;
+ * RL_ERR_INVALID_ARG on a NULL argument. */
+rl_status rl_plan_samples(const rl_plan* plan, int64_t* out);
+
 /* R f: Algorithm 1 (sec. 5).  d_img [batch][n][n] -> d_sino [batch][n_theta][n_s].
  * batch == 0 is a no-op. */
 rl_status radon_fwd(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch,

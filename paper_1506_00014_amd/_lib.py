@@ -32,6 +32,7 @@ EXPORTED = (
     "rl_plan_destroy",
     "rl_plan_geometry",
     "rl_workspace_bytes",
+    "rl_plan_samples",
     "radon_fwd",
     "radon_adj",
     "radon_transpose",
@@ -92,6 +93,8 @@ def load(path: str = LIB_PATH):
     lib.rl_plan_geometry.restype = c_int32
     lib.rl_workspace_bytes.argtypes = [c_void_p, c_int32, c_int32]
     lib.rl_workspace_bytes.restype = c_size_t
+    lib.rl_plan_samples.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int64)]
+    lib.rl_plan_samples.restype = c_int32
     for name in ("radon_fwd", "radon_adj", "radon_transpose"):
         f = getattr(lib, name)
         f.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]

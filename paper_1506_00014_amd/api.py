@@ -62,6 +62,12 @@ class RadonPlan:
     def workspace_bytes(self, batch, op):
         return int(self._lib.rl_workspace_bytes(self._ptr, batch, op))
 
+    def fine_samples(self):
+        """In-D fine log-polar samples of one slice over all partitions (interpolations per R)."""
+        out = ctypes.c_int64()
+        _lib.check("rl_plan_samples", self._lib.rl_plan_samples(self._ptr, ctypes.byref(out)))
+        return int(out.value)
+
     def _check_in(self, x, shape_tail, name):
         if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
             raise TypeError(f"{name} must be a CUDA (HIP) tensor")

@@ -377,6 +377,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   const int M = g.m, NF = d.n_fine;
   std::vector<double2> fine_cs((size_t)M * NF);
   std::vector<int2> fine_q((size_t)M * NF);
+  int64_t n_samples = 0;
   const double eps = 1e-9;  // samples within eps (in e^rho) of the boundary of D count as outside
   for (int p = 0; p < M; ++p) {
     for (int ti = 0; ti < NF; ++ti) {
@@ -395,6 +396,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
         }
       }
       fine_q[(size_t)p * NF + ti] = qr;
+      if (qr.y >= qr.x) n_samples += qr.y - qr.x + 1;
     }
   }
   std::vector<float4> dec(r);
@@ -574,6 +576,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   if ((st = check_hip(hipDeviceSynchronize(), "k_tau_table")) != RL_OK) return cleanup(st);
   plan->d_mem = mem;
   plan->d_mem_bytes = table_bytes;
+  plan->n_samples = n_samples;
   plan->d_adj = nullptr;
   plan->d_adj_bytes = 0;
   if ((st = build_adj_passes(plan)) != RL_OK) {
@@ -590,6 +593,12 @@ extern "C" void rl_plan_destroy(rl_plan* plan) {
   if (plan->d_mem) (void)hipFree(plan->d_mem);
   if (plan->d_adj) (void)hipFree(plan->d_adj);
   delete plan;
+}
+
+extern "C" rl_status rl_plan_samples(const rl_plan* plan, int64_t* out) {
+  if (!plan || !out) return fail(RL_ERR_INVALID_ARG, "NULL argument");
+  *out = plan->n_samples;
+  return RL_OK;
 }
 
 extern "C" rl_status rl_plan_geometry(const rl_plan* plan, rl_geom* out) {

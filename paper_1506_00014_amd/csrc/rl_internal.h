@@ -58,6 +58,7 @@ struct rl_plan {
   size_t d_mem_bytes;
   void* d_adj;  // device allocation holding the adjoint splat passes
   size_t d_adj_bytes;
+  int64_t n_samples;  // fine log-polar samples inside D of one slice, all partitions
 };
 
 namespace rl {

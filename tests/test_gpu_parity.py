@@ -246,3 +246,12 @@ def test_errors_on_device(dev):
     assert st == 0  # batch 0 is a no-op
     with pytest.raises(Exception):
         plan.forward(torch.zeros(64, 64, dtype=torch.float64, device=dev))
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
+def test_fine_sample_count(dev, case):
+    """The plan's count of in-D fine samples (work accounting) equals the oracle's sample set."""
+    n, nt, ns, m, kw = case
+    plan, og = get_plan(n, nt, ns, m, **kw)
+    ref = sum(oradon.fine_sample_points(og, p)[0].size for p in range(og.m))
+    assert plan.fine_samples() == ref
