@@ -181,43 +181,63 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
         }
       }
     }
-    Xlo = (int)floor(X0 + xmin) - 3;
+    Xlo = ((int)floor(X0 + xmin) - 3) & ~3;  // 4-aligned, for float4 loads
     Ylo = (int)floor(Y0 + ymin) - 3;
-    W = (int)floor(X0 + xmax) + 4 - Xlo + 1;
+    W = (((int)floor(X0 + xmax) + 4 - Xlo + 1) + 3) & ~3;
     H = (int)floor(Y0 + ymax) + 4 - Ylo + 1;
     Wp = W | 1;  // odd pitch spreads rows over the LDS banks
     staged = (long)Wp * H <= kFPatch;
     if (staged) {
-      // flat element order; (ly, lx) advance by the block stride without a division per
-      // element, four loads in flight per thread; indices outside the image wrap
-      const int tot = W * H;
-      const int dly = (int)blockDim.x / W, dlx = (int)blockDim.x - dly * W;
-      int ly = (int)threadIdx.x / W, lx = (int)threadIdx.x - ly * W;
-      for (int base = 0; base < tot; base += 4 * (int)blockDim.x) {
-        float v[4];
-        int dsti[4];
+      // groups of four consecutive pixels in flat order; (ly, lg) advance by the block stride
+      // without a division per group; a group inside the image is one float4 load (rows of
+      // 4-aligned groups are 16-byte aligned when n % 4 == 0), a group across the image edge
+      // wraps pixel by pixel
+      const int Wg = W >> 2, tot = Wg * H;
+      const int dly = (int)blockDim.x / Wg, dlg = (int)blockDim.x - dly * Wg;
+      int ly = (int)threadIdx.x / Wg, lg = (int)threadIdx.x - ly * Wg;
+      const bool vec_ok = (n & 3) == 0;
+      for (int base = 0; base < tot; base += 2 * (int)blockDim.x) {
+        float4 v[2];
+        int dsti[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 2; ++u) {
           const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
           dsti[u] = -1;
-          v[u] = 0.f;
           if (idx < tot) {
-            int gy = Ylo + ly, gx = Xlo + lx;
+            int gy = Ylo + ly;
             if (gy < 0 || gy >= n) gy = ((gy % n) + n) % n;
-            if (gx < 0 || gx >= n) gx = ((gx % n) + n) % n;
-            v[u] = img[(size_t)gy * n + gx];
-            dsti[u] = ly * Wp + lx;
+            const float* srow = img + (size_t)gy * n;
+            const int gx = Xlo + 4 * lg;
+            if (vec_ok && gx >= 0 && gx + 3 < n) {
+              v[u] = *reinterpret_cast<const float4*>(srow + gx);
+            } else {
+              float t[4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                int x = gx + e;
+                if (x < 0 || x >= n) x = ((x % n) + n) % n;
+                t[e] = srow[x];
+              }
+              v[u] = make_float4(t[0], t[1], t[2], t[3]);
+            }
+            dsti[u] = ly * Wp + 4 * lg;
           }
           ly += dly;
-          lx += dlx;
-          if (lx >= W) {
-            lx -= W;
+          lg += dlg;
+          if (lg >= Wg) {
+            lg -= Wg;
             ++ly;
           }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (dsti[u] >= 0) patch[dsti[u]] = v[u];
+        for (int u = 0; u < 2; ++u)
+          if (dsti[u] >= 0) {
+            float* d = patch + dsti[u];
+            d[0] = v[u].x;
+            d[1] = v[u].y;
+            d[2] = v[u].z;
+            d[3] = v[u].w;
+          }
       }
     }
   }
@@ -231,11 +251,12 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
     if (tl >= nft) continue;
     const int t = tlo + tl, q = q0 + ql;
     float v = 0.f;
+    // all LDS operands of the sample are read before the test (one round trip)
+    const int2 qr = sfq[tl];
+    const double2 tc = scs[tl];
+    const double E = se[ql];
     if (inside && q <= qlast) {
-      const int2 qr = sfq[tl];
-      if (q >= qr.x && q <= qr.y) {
-        const double2 tc = scs[tl];
-        const double E = se[ql];
+      if ((unsigned)(q - qr.x) <= (unsigned)(qr.y - qr.x) && qr.x <= qr.y) {
         const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
         if (staged) {
           // the 4 x 4 taps start at (kx - 1, ky - 1); the patch holds them (clamped for safety)
