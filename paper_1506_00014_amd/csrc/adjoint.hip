@@ -523,8 +523,8 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
   __shared__ int rcg[kASlots];
   __shared__ float4 rdw[kASlots];
   __shared__ double2 rcs[kASlots];
-  __shared__ float us[kUCap];   // coarse rows [cg0, cg0 + nur) x rho indices [wq, wq + span)
-  __shared__ double es[kECap];  // e^{rho_q} / (a_R dx) for q in [wq, wq + span)
+  __shared__ __align__(16) float us[kUCap];  // coarse rows [cg0, cg0 + nur) x rho [wq4, wq4 + span)
+  __shared__ double es[kECap];               // e^{rho_q} / (a_R dx) for q in [wq4, wq4 + span)
   const int n = P.n, r = P.r;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
   const int b = blockIdx.z;
@@ -555,36 +555,40 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
       rdw[sl] = P.dec[e.x - r * cg];
     }
     if (threadIdx.x == 0) rpre[nslot] = total;
-    // rho windows of the row copies
+    // rho windows of the row copies; a window starts at a multiple of 4 and spans a multiple
+    // of 4, so rows are copied as float4 (n_rho is a power of two)
     const int nur = cg1 - cg0 + 1;
-    const int wlen = min(kECap, kUCap / nur);
+    const int wlen = max(4, (min(kECap, kUCap / nur) - 4) & ~3);  // nur <= kARows + 3, so >= 32
     for (int wq = qlo; wq <= qhi; wq += wlen) {
-      const int span = min(wlen, qhi - wq + 1);
+      const int wq4 = wq & ~3;
+      const int wend = min(wq + wlen - 1, qhi);  // last rho index walked in this window
+      const int span = (wend - wq4 + 4) & ~3;    // copied: [wq4, wq4 + span)
       if (wq > qlo) __syncthreads();  // the previous window's walk is done with the copies
       {
-        constexpr int kIt = (kUCap + kAThreads - 1) / kAThreads;
-        const int tot = nur * span;
-        // element i = threadIdx.x + it * kAThreads is (row, qq) = divmod(i, span); both
-        // advance by the block stride without a division per element
-        const int drow = kAThreads / span, dqq = kAThreads - drow * span;
-        int row = (int)threadIdx.x / span, qq = (int)threadIdx.x - row * span;
-        float tmp[kIt];
+        constexpr int kIt = (kUCap / 4 + kAThreads - 1) / kAThreads;
+        const int sg = span >> 2, tot = nur * sg;
+        // group i = threadIdx.x + it * kAThreads is (row, g) = divmod(i, sg); both advance by
+        // the block stride without a division per group
+        const int drow = kAThreads / sg, dg = kAThreads - drow * sg;
+        int row = (int)threadIdx.x / sg, g = (int)threadIdx.x - row * sg;
+        float4 tmp[kIt];
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
           const int i = threadIdx.x + it * kAThreads;
-          tmp[it] = i < tot ? Ub[(size_t)(cg0 + row) * P.n_rho + wq + qq] : 0.f;
+          tmp[it] = i < tot ? *reinterpret_cast<const float4*>(Ub + (size_t)(cg0 + row) * P.n_rho + wq4 + 4 * g)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
           row += drow;
-          qq += dqq;
-          if (qq >= span) {
-            qq -= span;
+          g += dg;
+          if (g >= sg) {
+            g -= sg;
             ++row;
           }
         }
-        const double e = threadIdx.x < span ? P.erho[wq + threadIdx.x] : 0.0;
+        const double e = threadIdx.x < span ? P.erho[wq4 + threadIdx.x] : 0.0;
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
           const int i = threadIdx.x + it * kAThreads;
-          if (i < tot) us[i] = tmp[it];
+          if (i < tot) reinterpret_cast<float4*>(us)[i] = tmp[it];
         }
         if (threadIdx.x < span) es[threadIdx.x] = e;
       }
@@ -607,7 +611,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
         sw.cy = tcs.y;
         const int q0 = rq0[k] + (idx - rpre[k]) * seglen;
         sw.qbeg = max(q0, wq);
-        sw.qend = min(min(q0 + seglen - 1, rcnt[k]), wq + span - 1);
+        sw.qend = min(min(q0 + seglen - 1, rcnt[k]), wend);
         sw.ux0 = ux0;
         sw.ux1 = ux1;
         sw.uy0 = uy0;
@@ -624,7 +628,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
           sw.dw[i] = ok ? dwv[i] * (1.0f / 36.0f) : 0.f;
           sw.roff[i] = (min(max(row, cg0), cg1) - cg0) * span;
         }
-        splat_walk(sw, acc, us, es, wq);
+        splat_walk(sw, acc, us, es, wq4);
       }
     }
   }
