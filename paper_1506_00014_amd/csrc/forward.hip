@@ -18,9 +18,12 @@
 namespace rl {
 
 // ------------------------------------------------------------------ prefilter
-constexpr int kPT = 32;             // output tile side
-constexpr int kPI = kPT + 2 * kPrefR;  // input tile side
+constexpr int kPT = 64;                // output tile side
+constexpr int kPI = kPT + 2 * kPrefR;  // input tile side (96)
 
+// Block: one kPT x kPT output tile.  The (kPT + 32)^2 input tile (periodic wrap) is staged in
+// LDS; the row pass filters all kPI rows into kPT columns, the column pass the kPT columns;
+// each thread filters a run of outputs from a register window.
 __global__ __launch_bounds__(kThreads) void k_prefilter(const float* __restrict__ in, float* __restrict__ out,
                                                         int n, float scale, const float* __restrict__ pref) {
   __shared__ float tin[kPI][kPI + 1];
@@ -30,38 +33,63 @@ __global__ __launch_bounds__(kThreads) void k_prefilter(const float* __restrict_
   const int ty0 = blockIdx.y * kPT, tx0 = blockIdx.x * kPT;
   const float* src = in + (size_t)b * n * n;
   if (threadIdx.x <= kPrefR) q[threadIdx.x] = pref[threadIdx.x];
-  for (int idx = threadIdx.x; idx < kPI * kPI; idx += blockDim.x) {
-    const int ly = idx / kPI, lx = idx % kPI;
-    int gy = (ty0 - kPrefR + ly) % n;
-    int gx = (tx0 - kPrefR + lx) % n;
-    gy += gy < 0 ? n : 0;
-    gx += gx < 0 ? n : 0;
-    tin[ly][lx] = src[(size_t)gy * n + gx];
+  {
+    // flat element order, (ly, lx) stepped by the block stride; 4 loads in flight per thread
+    constexpr int tot = kPI * kPI;
+    constexpr int dly = kThreads / kPI, dlx = kThreads - dly * kPI;
+    int ly = (int)threadIdx.x / kPI, lx = (int)threadIdx.x - ly * kPI;
+    for (int base = 0; base < tot; base += 4 * kThreads) {
+      float v[4];
+      int dl[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = base + u * kThreads + (int)threadIdx.x;
+        dl[u] = -1;
+        if (idx < tot) {
+          int gy = ty0 - kPrefR + ly, gx = tx0 - kPrefR + lx;
+          if (gy < 0 || gy >= n) gy = ((gy % n) + n) % n;
+          if (gx < 0 || gx >= n) gx = ((gx % n) + n) % n;
+          v[u] = src[(size_t)gy * n + gx];
+          dl[u] = ly * (kPI + 1) + lx;
+        }
+        ly += dly;
+        lx += dlx;
+        if (lx >= kPI) {
+          lx -= kPI;
+          ++ly;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (dl[u] >= 0) (&tin[0][0])[dl[u]] = v[u];
+    }
   }
   __syncthreads();
   float qk[kPrefR + 1];
 #pragma unroll
   for (int k = 0; k <= kPrefR; ++k) qk[k] = q[k];
-  // rows: each thread filters 8 consecutive outputs of one row from a register window
+  // rows: kPI rows x (kPT / 8) runs of 8 outputs = 768 runs, 3 per thread
   {
-    constexpr int R = 8;
-    const int row = threadIdx.x / (kPT / R), seg = threadIdx.x % (kPT / R);
-    float x[R + 2 * kPrefR];
+    constexpr int R = 8, runs = kPI * (kPT / R);
+    for (int rid = threadIdx.x; rid < runs; rid += kThreads) {
+      const int row = rid / (kPT / R), seg = rid % (kPT / R);
+      float x[R + 2 * kPrefR];
 #pragma unroll
-    for (int i = 0; i < R + 2 * kPrefR; ++i) x[i] = tin[row][seg * R + i];
+      for (int i = 0; i < R + 2 * kPrefR; ++i) x[i] = tin[row][seg * R + i];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      float acc = qk[0] * x[j + kPrefR];
+      for (int j = 0; j < R; ++j) {
+        float acc = qk[0] * x[j + kPrefR];
 #pragma unroll
-      for (int k = 1; k <= kPrefR; ++k) acc += qk[k] * (x[j + kPrefR - k] + x[j + kPrefR + k]);
-      trow[row][seg * R + j] = acc;
+        for (int k = 1; k <= kPrefR; ++k) acc += qk[k] * (x[j + kPrefR - k] + x[j + kPrefR + k]);
+        trow[row][seg * R + j] = acc;
+      }
     }
   }
   __syncthreads();
-  // columns: each thread filters 4 consecutive outputs of one column
+  // columns: kPT columns x 4 runs of 16 outputs, one run per thread
   float* dst = out + (size_t)b * n * n;
   {
-    constexpr int R = 4;
+    constexpr int R = kPT / (kThreads / kPT);  // 16
     const int col = threadIdx.x % kPT, seg = threadIdx.x / kPT;
     float y[R + 2 * kPrefR];
 #pragma unroll
