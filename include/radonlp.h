@@ -180,6 +180,36 @@ rl_status rl_profile_stop(void);
 int32_t rl_profile_count(void);
 rl_status rl_profile_record(int32_t i, const char** name, float* ms);
 
+/* ---------------------------------------------------------------- ragged batches
+ * A ragged batch is a fixed set of `count` slices of possibly different geometries (sec. 6
+ * times stacks of slices; here each slice names one of `nplans` plans, several slices may
+ * share one), each with its own image buffer d_imgs[i] ([n][n] of its plan) and sinogram
+ * buffer d_sinos[i] ([n_theta][n_s]).  rl_batch_create copies the pointer lists to the device
+ * and groups the slices by plan; it is synchronous and allocates.  rl_batch_fwd computes
+ * d_sinos[i] = R d_imgs[i] and rl_batch_adj d_imgs[i] = R# d_sinos[i] for every slice, as one
+ * batched call per plan (slices gathered into the workspace, results scattered back).  Those
+ * two calls enqueue kernels on `stream` only: no allocation, host synchronisation or host
+ * read, so a caller may capture them in a HIP graph and replay it with new buffer contents.
+ * The buffers stay owned by the caller and must stay valid while the batch is used; input
+ * and output buffers must not overlap.  tune_cache is reserved for launch-parameter tuning
+ * and must be NULL.  Errors: RL_ERR_INVALID_ARG for NULL lists, count < 0, a plan index out
+ * of range, a plan built on another device or a non-NULL tune_cache; RL_ERR_WORKSPACE for a
+ * workspace smaller than rl_batch_workspace_bytes(batch, op) or not 256-byte aligned. */
+typedef struct rl_batch rl_batch;
+
+rl_status rl_batch_create(const rl_plan* const* plans, int32_t nplans, const int32_t* plan_of_slice,
+                          float* const* d_imgs, float* const* d_sinos, int32_t count, const char* tune_cache,
+                          rl_batch** out);
+
+/* Workspace bytes rl_batch_fwd (op = RL_OP_FWD) or rl_batch_adj (RL_OP_ADJ) needs. */
+size_t rl_batch_workspace_bytes(const rl_batch* batch, rl_op op);
+
+rl_status rl_batch_fwd(const rl_batch* batch, void* d_ws, size_t ws_bytes, hipStream_t stream);
+rl_status rl_batch_adj(const rl_batch* batch, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Release a batch (not its buffers or plans).  NULL is a no-op. */
+void rl_batch_destroy(rl_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libradonlp.so")
 
 RL_OK = 0
+RL_ERR_INVALID_ARG, RL_ERR_GEOMETRY, RL_ERR_WORKSPACE, RL_ERR_HIP = 1, 2, 3, 4
 STATUS_NAMES = {
     0: "RL_OK",
     1: "RL_ERR_INVALID_ARG",
@@ -43,6 +44,11 @@ EXPORTED = (
     "rl_profile_stop",
     "rl_profile_count",
     "rl_profile_record",
+    "rl_batch_create",
+    "rl_batch_workspace_bytes",
+    "rl_batch_fwd",
+    "rl_batch_adj",
+    "rl_batch_destroy",
 )
 
 
@@ -113,6 +119,18 @@ def load(path: str = LIB_PATH):
     lib.rl_profile_count.restype = c_int32
     lib.rl_profile_record.argtypes = [c_int32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float)]
     lib.rl_profile_record.restype = c_int32
+    lib.rl_batch_create.argtypes = [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(c_int32),
+                                    ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_int32, ctypes.c_char_p,
+                                    ctypes.POINTER(c_void_p)]
+    lib.rl_batch_create.restype = c_int32
+    lib.rl_batch_workspace_bytes.argtypes = [c_void_p, c_int32]
+    lib.rl_batch_workspace_bytes.restype = c_size_t
+    for name in ("rl_batch_fwd", "rl_batch_adj"):
+        f = getattr(lib, name)
+        f.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
+        f.restype = c_int32
+    lib.rl_batch_destroy.argtypes = [c_void_p]
+    lib.rl_batch_destroy.restype = None
     _lib = lib
     return lib
 

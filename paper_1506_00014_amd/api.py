@@ -186,3 +186,63 @@ class RadonFn(torch.autograd.Function):
 def radon(img, plan):
     """Differentiable R f."""
     return RadonFn.apply(img, plan)
+
+
+class RaggedBatch:
+    """A fixed set of slices of possibly different geometries, transformed together.
+
+    items: list of (plan, image, sinogram) with image [n][n] and sinogram [n_theta][n_s]
+    float32 CUDA tensors of that plan (contiguous).  forward() writes every sinogram from its
+    image (R), adjoint() every image from its sinogram (R#), each as one batched call per plan,
+    enqueued on the current stream; neither allocates, so both can be captured in a CUDA (HIP)
+    graph and replayed after the tensors' contents change.  The tensors must stay alive.
+    """
+
+    def __init__(self, items):
+        lib = _lib.load()
+        plans, index = [], {}
+        plan_of, imgs, sinos = [], [], []
+        for plan, img, sino in items:
+            g = plan.geom
+            plan._check_in(img, (g["n"], g["n"]), "image")
+            plan._check_in(sino, (g["n_theta"], g["n_s"]), "sinogram")
+            if img.dim() != 2 or sino.dim() != 2 or not img.is_contiguous() or not sino.is_contiguous():
+                raise ValueError("ragged batch buffers must be contiguous 2-D tensors")
+            if id(plan) not in index:
+                index[id(plan)] = len(plans)
+                plans.append(plan)
+            plan_of.append(index[id(plan)])
+            imgs.append(img)
+            sinos.append(sino)
+        n = len(imgs)
+        self._keep = (plans, imgs, sinos)
+        self.device = plans[0].device if plans else torch.device("cuda", torch.cuda.current_device())
+        c_plans = (ctypes.c_void_p * max(1, len(plans)))(*[p._ptr.value for p in plans])
+        c_of = (ctypes.c_int32 * max(1, n))(*plan_of)
+        c_imgs = (ctypes.c_void_p * max(1, n))(*[t.data_ptr() for t in imgs])
+        c_sinos = (ctypes.c_void_p * max(1, n))(*[t.data_ptr() for t in sinos])
+        self._ptr = ctypes.c_void_p()
+        self._lib = lib
+        with torch.cuda.device(self.device):
+            _lib.check("rl_batch_create", lib.rl_batch_create(c_plans, len(plans), c_of, c_imgs, c_sinos, n, None,
+                                                              ctypes.byref(self._ptr)))
+            nbytes = max(int(lib.rl_batch_workspace_bytes(self._ptr, op)) for op in (0, 1))
+            self._ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        ptr = getattr(self, "_ptr", None)
+        if ptr is not None and ptr.value:
+            self._lib.rl_batch_destroy(ptr)
+            self._ptr = None
+
+    def _run(self, fn, name):
+        with torch.cuda.device(self.device):
+            _lib.check(name, fn(self._ptr, ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(),
+                                _stream_ptr(self.device)))
+
+    def forward(self):
+        self._run(self._lib.rl_batch_fwd, "rl_batch_fwd")
+
+    def adjoint(self):
+        self._run(self._lib.rl_batch_adj, "rl_batch_adj")
+

@@ -76,16 +76,17 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
   rfft_post(sh, nc, P.tw, P.tw_len, [&](int k, float2 x) { dst[k] = x; });
 }
 
+rl_status prepare_adjoint_launches(const rl_plan* p) {
+  return ensure_dyn_lds((const void*)k_splat_rfft, (size_t)p->d.n_rho * sizeof(double),
+                        "hipFuncSetAttribute(k_splat_rfft)");
+}
+
 rl_status launch_splat_rfft(const rl_plan* p, const float* sino, float2* spec, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   const size_t lds = (size_t)d.n_rho * sizeof(double);
   dim3 grid(d.n_own, batch * d.m);
-  if (lds > 65536) {
-    rl_status st = check_hip(hipFuncSetAttribute((const void*)k_splat_rfft, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)lds),
-                             "hipFuncSetAttribute(k_splat_rfft)");
-    if (st != RL_OK) return st;
-  }
+  rl_status st = ensure_dyn_lds((const void*)k_splat_rfft, lds, "hipFuncSetAttribute(k_splat_rfft)");
+  if (st != RL_OK) return st;
   RL_LAUNCH("k_splat_rfft", k_splat_rfft, grid, dim3(kThreads), lds, s, d, sino, spec);
   return check_launch("k_splat_rfft");
 }

@@ -324,17 +324,17 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
   }
 }
 
+static size_t cart2lp_lds(const DevPlan& d) {
+  const int nft = d.r * (kFRows + 3) - 1;
+  return (size_t)(kFPatch + nft * kFQ) * sizeof(float) + (size_t)nft * (sizeof(double2) + sizeof(int2)) +
+         kFQ * sizeof(double);
+}
+
 rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
-  const int nft = d.r * (kFRows + 3) - 1;
-  const size_t lds = (size_t)(kFPatch + nft * kFQ) * sizeof(float) + (size_t)nft * (sizeof(double2) + sizeof(int2)) +
-                     kFQ * sizeof(double);
-  if (lds > 65536) {
-    rl_status st = check_hip(hipFuncSetAttribute((const void*)k_cart2lp, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)lds),
-                             "hipFuncSetAttribute(k_cart2lp)");
-    if (st != RL_OK) return st;
-  }
+  const size_t lds = cart2lp_lds(d);
+  rl_status st = ensure_dyn_lds((const void*)k_cart2lp, lds, "hipFuncSetAttribute(k_cart2lp)");
+  if (st != RL_OK) return st;
   dim3 grid((d.n_rho + kFQ - 1) / kFQ, (d.n_sup + kFRows - 1) / kFRows, batch * d.m);
   RL_LAUNCH("k_cart2lp", k_cart2lp, grid, dim3(kThreads), lds, s, d, c, u);
   return check_launch("k_cart2lp");
@@ -479,17 +479,45 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
 }
 
 template <int K1, int K2>
+static int theta_cw() {
+  return max(1, min(8, kThreads / max(K1, K2)));
+}
+
+template <int K1, int K2>
+static size_t theta_lds() {
+  return (size_t)theta_cw<K1, K2>() * (K1 * (K2 + 1) + 1) * sizeof(float2);
+}
+
+template <int K1, int K2>
+static rl_status theta_prepare() {
+  return ensure_dyn_lds((const void*)k_theta_conv<K1, K2>, theta_lds<K1, K2>(), "hipFuncSetAttribute(k_theta_conv)");
+}
+
+rl_status prepare_forward_launches(const rl_plan* p) {
+  rl_status st = ensure_dyn_lds((const void*)k_cart2lp, cart2lp_lds(p->d), "hipFuncSetAttribute(k_cart2lp)");
+  if (st != RL_OK) return st;
+  switch (p->d.k_theta) {
+    case 8: return theta_prepare<8, 1>();
+    case 16: return theta_prepare<16, 1>();
+    case 32: return theta_prepare<32, 1>();
+    case 64: return theta_prepare<32, 2>();
+    case 128: return theta_prepare<32, 4>();
+    case 256: return theta_prepare<32, 8>();
+    case 512: return theta_prepare<32, 16>();
+    case 1024: return theta_prepare<32, 32>();
+    case 2048: return theta_prepare<32, 64>();
+    default: return fail(RL_ERR_INTERNAL, "unsupported k_theta");
+  }
+}
+
+template <int K1, int K2>
 static rl_status launch_theta_conv_t(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out,
                                      int out_rows, int out_off, bool conj, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
-  const int cw = max(1, min(8, kThreads / max(K1, K2)));
-  const size_t lds = (size_t)cw * (K1 * (K2 + 1) + 1) * sizeof(float2);
-  if (lds > 65536) {
-    rl_status st = check_hip(hipFuncSetAttribute((const void*)k_theta_conv<K1, K2>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-                             "hipFuncSetAttribute(k_theta_conv)");
-    if (st != RL_OK) return st;
-  }
+  const int cw = theta_cw<K1, K2>();
+  const size_t lds = theta_lds<K1, K2>();
+  rl_status st = ensure_dyn_lds((const void*)k_theta_conv<K1, K2>, lds, "hipFuncSetAttribute(k_theta_conv)");
+  if (st != RL_OK) return st;
   dim3 grid((d.nc + 1 + cw - 1) / cw, batch * d.m);
   RL_LAUNCH("k_theta_conv", (k_theta_conv<K1, K2>), grid, dim3(kThreads), lds, s, d, in, in_rows, in_off, out,
             out_rows, out_off, conj ? 1 : 0, cw);

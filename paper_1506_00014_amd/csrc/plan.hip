@@ -2,6 +2,10 @@
 // log-polar kernel (computed on the device in FP64), twiddles; error reporting; workspace.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -221,6 +225,20 @@ rl_status check_hip(hipError_t e, const char* what) {
 }
 
 rl_status check_launch(const char* what) { return check_hip(hipGetLastError(), what); }
+
+rl_status ensure_dyn_lds(const void* fn, size_t lds, const char* what) {
+  if (lds <= 65536) return RL_OK;
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, size_t> done;  // (kernel, device) -> limit set
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RL_ERR_HIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& have = done[std::make_pair(fn, dev)];
+  if (have >= lds) return RL_OK;
+  rl_status st = check_hip(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), what);
+  if (st == RL_OK) have = lds;
+  return st;
+}
 
 rl_status check_plan_device(const rl_plan* plan) {
   int dev = -1;
@@ -581,6 +599,11 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   plan->d_adj_bytes = 0;
   if ((st = build_adj_passes(plan)) != RL_OK) {
     plan->d_mem = nullptr;  // freed by cleanup
+    return cleanup(st);
+  }
+  if ((st = prepare_forward_launches(plan)) != RL_OK || (st = prepare_adjoint_launches(plan)) != RL_OK) {
+    if (plan->d_adj) (void)hipFree(plan->d_adj);
+    plan->d_mem = nullptr;
     return cleanup(st);
   }
   cleanup(RL_OK);

@@ -69,6 +69,9 @@ rl_status fail(rl_status code, const std::string& msg);
 rl_status check_hip(hipError_t e, const char* what);
 rl_status check_launch(const char* what);
 rl_status check_plan_device(const rl_plan* plan);
+// Raise a kernel's dynamic LDS limit above the default 64 KiB on the current device, once:
+// later calls with the same or a smaller size make no HIP call, so launches stay capturable.
+rl_status ensure_dyn_lds(const void* fn, size_t lds, const char* what);
 
 struct WsLayout {
   size_t off[6];
@@ -108,5 +111,8 @@ rl_status launch_irfft_rows(const rl_plan* p, const float2* spec, float* out, in
                             hipStream_t s);
 // Plan time: build the adjoint splat passes (allocates plan->d_adj, fills the adj_* fields).
 rl_status build_adj_passes(rl_plan* p);
+// Plan time: raise the LDS limits of the kernels this plan launches (see ensure_dyn_lds).
+rl_status prepare_forward_launches(const rl_plan* p);
+rl_status prepare_adjoint_launches(const rl_plan* p);
 
 }  // namespace rl
