@@ -173,6 +173,60 @@ def cpu_baseline(g, seed=303, parts=3):
     }
 
 
+def ragged_detail(torch, log, count=256, seed=401):
+    """Ragged batch: `count` slices with N drawn from {256, 512, 768, 1024} (N x N sinograms),
+    R and R# for the whole set as one replay of a captured graph vs one plain call per slice."""
+    import numpy as np
+
+    from paper_1506_00014_amd import RadonPlan, RaggedBatch
+
+    rng = np.random.default_rng(seed)
+    sizes = [int(x) for x in rng.choice([256, 512, 768, 1024], size=count)]
+    plans = {n: RadonPlan(n, n, n) for n in sorted(set(sizes))}
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    items = [(plans[n], torch.rand(n, n, generator=gen, device=dev), torch.empty(n, n, device=dev)) for n in sizes]
+    batch = RaggedBatch(items)
+    ws1 = {n: torch.empty(max(p.workspace_bytes(1, op) for op in (0, 1)), dtype=torch.uint8, device=dev)
+           for n, p in plans.items()}
+    out = {"slices": count, "sizes": {str(n): sizes.count(n) for n in sorted(set(sizes))}}
+    for name, run, plain in (("R", batch.forward, lambda p, i, s: p.forward(i, ws1[i.shape[0]])),
+                             ("R#", batch.adjoint, lambda p, i, s: p.adjoint(s, ws1[i.shape[0]]))):
+        run()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            with torch.cuda.graph(graph, stream=st):
+                run()
+        torch.cuda.current_stream().wait_stream(st)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        graph.replay()
+        ev0.record()
+        for _ in range(3):
+            graph.replay()
+        ev1.record()
+        torch.cuda.synchronize()
+        t_graph = ev0.elapsed_time(ev1) / 3
+        for p, i, s in items:
+            plain(p, i, s)
+        torch.cuda.synchronize()
+        ev0.record()
+        for p, i, s in items:
+            plain(p, i, s)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_plain = ev0.elapsed_time(ev1)
+        out[name] = {"graph_slices_per_s": round(count / (t_graph / 1000.0), 1),
+                     "plain_slices_per_s": round(count / (t_plain / 1000.0), 1),
+                     "graph_over_plain": round(t_plain / t_graph, 3)}
+        log(f"ragged {name}: {out[name]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +236,7 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch detail measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (FETCH_SIZE / WRITE_SIZE calibration)")
     args = ap.parse_args()
@@ -305,6 +360,8 @@ def main():
             rec["batched_over_plain"] = round(tp / tb, 3)
         detail["per_op"][op] = rec
         log(f"{op}: {rec}")
+    if not args.no_ragged:
+        detail["ragged_batch"] = ragged_detail(torch, log)
     detail["paper_context"] = ("GTX 770, CUDA 7, FP32, M=3, N_theta=1.5N: R# 9.9e-2 s per 2048^2 slice "
                                "(10.1 slices/s); one R + one R# 0.205 s per slice (4.9 slices/s); context only")
 
