@@ -113,9 +113,11 @@ rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int ba
 }
 
 // ------------------------------------------------------------------ cart -> log-polar
-constexpr int kFQ = 32;         // rho indices per block
+constexpr int kFQ = 64;         // rho indices per block: one per lane of a wave
 constexpr int kFRows = 8;       // coarse rows per block
-constexpr int kFPatch = 6144;   // floats of the LDS image patch
+constexpr int kFPatch = 8448;   // floats of the LDS image patch
+constexpr int kFThreads = 512;  // threads per block
+static_assert(kFQ == 64, "the sample loop maps rho indices to the lanes of a wave");
 
 // Bicubic sample of the spline coefficients at index position (X, Y); taps read through `tap`.
 template <class Tap>
@@ -138,11 +140,11 @@ __device__ __forceinline__ float bicubic_at(double X, double Y, int n, Tap tap) 
 
 // Block: kFQ consecutive rho indices and kFRows coarse rows of one (slice, partition).
 // 1) The fine rays feeding those rows sweep an annular sector of the image; its bounding box
-//    is staged in LDS (global gathers if it does not fit).  2) Each wave computes 8 x 8
-//    patches (8 fine rows x 8 rho indices, a compact footprint) of bicubic samples into an
-//    LDS buffer; samples outside D are zero.  3) Each coarse sample is the decimation filter
-//    over the fine rows around it, times e^rho.
-__global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __restrict__ c, float* __restrict__ u) {
+//    is staged in LDS (global gathers if it does not fit).  2) Each wave computes the bicubic
+//    samples of one fine ray at a time, a lane per rho index, into an LDS buffer; samples
+//    outside D are zero.  3) Each coarse sample is the decimation filter over the fine rows
+//    around it, times e^rho.
+__global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const float* __restrict__ c, float* __restrict__ u) {
   extern __shared__ float smem[];
   float* patch = smem;
   float* vbuf = smem + kFPatch;
@@ -167,8 +169,15 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
   double* se = reinterpret_cast<double*>(sfq + nftmax);
   const int tclo = max(tlo, P.t_min), tchi = min(thi, P.t_min + P.n_fine - 1);
   const int qlast = min(q0 + kFQ, P.n_rho) - 1;
-  // stage the tables; is any sample of the block inside D?
-  int inside = 0;
+  // image box of the block's samples, built with the plan (W == 0: no sample inside D)
+  const int4 box = P.fbox[((size_t)m * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x];
+  if (box.z == 0) {
+    for (int o = threadIdx.x; o < (i1 - i0) * kFQ; o += blockDim.x) {
+      const int il = o / kFQ, ql = o - il * kFQ;
+      if (q0 + ql <= qlast) u[((size_t)bm * P.n_sup + i0 + il) * P.n_rho + q0 + ql] = 0.f;
+    }
+    return;  // uniform across the block
+  }
   for (int tl = threadIdx.x; tl < nft; tl += blockDim.x) {
     const int t = tlo + tl;
     int2 qr = make_int2(1, 0);  // empty
@@ -179,42 +188,12 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
     }
     sfq[tl] = qr;
     scs[tl] = tc;
-    inside |= (qr.x <= qr.y && qr.x <= qlast && qr.y >= q0);
   }
   if (threadIdx.x < kFQ) se[threadIdx.x] = q0 + (int)threadIdx.x <= qlast ? P.erho[q0 + threadIdx.x] : 0.0;
-  inside = __syncthreads_or(inside);
-  int Xlo = 0, Ylo = 0, W = 0, H = 0, Wp = 1;
-  bool staged = false;
-  if (inside) {
-    // bounding box of the sector: E in [erho[q0], erho[qlast]], directions of rays tclo..tchi
-    const double Elo = P.erho[q0], Ehi = P.erho[qlast];
-    const double2 ca = cs[tclo - P.t_min], cb2 = cs[tchi - P.t_min];
-    double xmin = fmin(fmin(Elo * ca.x, Ehi * ca.x), fmin(Elo * cb2.x, Ehi * cb2.x));
-    double xmax = fmax(fmax(Elo * ca.x, Ehi * ca.x), fmax(Elo * cb2.x, Ehi * cb2.x));
-    double ymin = fmin(fmin(Elo * ca.y, Ehi * ca.y), fmin(Elo * cb2.y, Ehi * cb2.y));
-    double ymax = fmax(fmax(Elo * ca.y, Ehi * ca.y), fmax(Elo * cb2.y, Ehi * cb2.y));
-    {
-      // the outer arc bulges past its chord where it crosses an axis direction
-      const double pa = atan2(ca.y, ca.x), pb = atan2(cb2.y, cb2.x);
-      const double lo = fmin(pa, pb), hi = fmax(pa, pb);
-      const double half_pi = 1.5707963267948966;
-      for (int k = -2; k <= 2; ++k) {
-        const double ax = k * half_pi;
-        if (ax > lo && ax < hi) {
-          const int kk = (k + 4) & 3;
-          if (kk == 0) xmax = fmax(xmax, Ehi);
-          if (kk == 2) xmin = fmin(xmin, -Ehi);
-          if (kk == 1) ymax = fmax(ymax, Ehi);
-          if (kk == 3) ymin = fmin(ymin, -Ehi);
-        }
-      }
-    }
-    Xlo = ((int)floor(X0 + xmin) - 3) & ~3;  // 4-aligned, for float4 loads
-    Ylo = (int)floor(Y0 + ymin) - 3;
-    W = (((int)floor(X0 + xmax) + 4 - Xlo + 1) + 3) & ~3;
-    H = (int)floor(Y0 + ymax) + 4 - Ylo + 1;
-    Wp = W | 1;  // odd pitch spreads rows over the LDS banks
-    staged = (long)Wp * H <= kFPatch;
+  const int Xlo = box.x, Ylo = box.y, W = box.z, H = box.w;
+  const int Wp = W | 1;  // odd pitch spreads rows over the LDS banks
+  const bool staged = Wp * H <= kFPatch;
+  {
     if (staged) {
       // groups of four consecutive pixels in flat order; (ly, lg) advance by the block stride
       // without a division per group; a group inside the image is one float4 load (rows of
@@ -270,40 +249,33 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
     }
   }
   __syncthreads();
-  // fine samples, 8 x 8 patches per wave
-  const int npt = (nft + 7) >> 3;
-  const int npatch = npt * (kFQ / 8);
-  for (int pidx = wave; pidx < npatch; pidx += nwave) {
-    const int tl = (pidx / (kFQ / 8)) * 8 + (lane >> 3);
-    const int ql = (pidx % (kFQ / 8)) * 8 + (lane & 7);
-    if (tl >= nft) continue;
-    const int t = tlo + tl, q = q0 + ql;
-    float v = 0.f;
-    // all LDS operands of the sample are read before the test (one round trip)
+  // fine samples: a wave takes one ray (its table entries are wave-uniform LDS broadcasts),
+  // lane l the rho index q0 + l
+  const int ql = lane, q = q0 + lane;
+  const double E = se[ql];
+  for (int tl = wave; tl < nft; tl += nwave) {
     const int2 qr = sfq[tl];
     const double2 tc = scs[tl];
-    const double E = se[ql];
-    if (inside && q <= qlast) {
-      if ((unsigned)(q - qr.x) <= (unsigned)(qr.y - qr.x) && qr.x <= qr.y) {
-        const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
-        if (staged) {
-          // the 4 x 4 taps start at (kx - 1, ky - 1); the patch holds them (clamped for safety)
-          const double fx = floor(X), fy = floor(Y);
-          float wx[4], wy[4];
-          bspline_w6((float)(X - fx), wx);
-          bspline_w6((float)(Y - fy), wy);
-          const int bx = min(max((int)fx - 1 - Xlo, 0), W - 4);
-          const int by = min(max((int)fy - 1 - Ylo, 0), H - 4);
-          const float* p0 = patch + by * Wp + bx;
+    float v = 0.f;
+    if (q <= qlast && q >= qr.x && q <= qr.y) {
+      const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
+      if (staged) {
+        // the 4 x 4 taps start at (kx - 1, ky - 1); the patch holds them (clamped for safety)
+        const double fx = floor(X), fy = floor(Y);
+        float wx[4], wy[4];
+        bspline_w6((float)(X - fx), wx);
+        bspline_w6((float)(Y - fy), wy);
+        const int bx = min(max((int)fx - 1 - Xlo, 0), W - 4);
+        const int by = min(max((int)fy - 1 - Ylo, 0), H - 4);
+        const float* p0 = patch + by * Wp + bx;
 #pragma unroll
-          for (int bb = 0; bb < 4; ++bb) {
-            const float* pr = p0 + bb * Wp;
-            v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
-          }
-          v *= 1.0f / 36.0f;
-        } else {
-          v = bicubic_at(X, Y, n, [&](int x, int y) { return img[(size_t)wrap1(y, n) * n + wrap1(x, n)]; });
+        for (int bb = 0; bb < 4; ++bb) {
+          const float* pr = p0 + bb * Wp;
+          v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
         }
+        v *= 1.0f / 36.0f;
+      } else {
+        v = bicubic_at(X, Y, n, [&](int x, int y) { return img[(size_t)wrap1(y, n) * n + wrap1(x, n)]; });
       }
     }
     vbuf[tl * kFQ + ql] = v;
@@ -324,6 +296,61 @@ __global__ __launch_bounds__(kThreads) void k_cart2lp(DevPlan P, const float* __
   }
 }
 
+// Image boxes of the forward blocks (plan time, host): for block (bx, by) of partition m,
+// (Xlo, Ylo, W, H) bounds the image indices of every 4 x 4 tap set of its fine samples inside
+// D: the annular sector swept by its rays between e^rho of its first and last rho index,
+// widened where the outer arc crosses an axis direction, plus the taps' reach.  Xlo and W are
+// multiples of 4 (float4 staging).  W = 0 marks a block none of whose samples lies in D.
+std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& cs_all,
+                                  const std::vector<int2>& fq_all, const std::vector<double>& erho) {
+  const int gx = (d.n_rho + kFQ - 1) / kFQ, gy = (d.n_sup + kFRows - 1) / kFRows, r = d.r;
+  std::vector<int4> out((size_t)d.m * gy * gx, make_int4(0, 0, 0, 0));
+  for (int m = 0; m < d.m; ++m) {
+    const double2* cs = cs_all.data() + (size_t)m * d.n_fine;
+    const int2* fq = fq_all.data() + (size_t)m * d.n_fine;
+    for (int by = 0; by < gy; ++by) {
+      const int i0 = by * kFRows, i1 = std::min(i0 + kFRows, d.n_sup);
+      const int tlo = r * (i0 - 2) + 1, thi = r * (i1 + 1) - 1;
+      const int tclo = std::max(tlo, d.t_min), tchi = std::min(thi, d.t_min + d.n_fine - 1);
+      for (int bx = 0; bx < gx; ++bx) {
+        const int q0 = bx * kFQ, qlast = std::min(q0 + kFQ, d.n_rho) - 1;
+        bool inside = false;
+        for (int t = tclo; t <= tchi && !inside; ++t) {
+          const int2 qr = fq[t - d.t_min];
+          inside = qr.x <= qr.y && qr.x <= qlast && qr.y >= q0;
+        }
+        if (!inside) continue;
+        const double Elo = erho[q0], Ehi = erho[qlast];
+        const double2 ca = cs[tclo - d.t_min], cb = cs[tchi - d.t_min];
+        double xmin = std::min(std::min(Elo * ca.x, Ehi * ca.x), std::min(Elo * cb.x, Ehi * cb.x));
+        double xmax = std::max(std::max(Elo * ca.x, Ehi * ca.x), std::max(Elo * cb.x, Ehi * cb.x));
+        double ymin = std::min(std::min(Elo * ca.y, Ehi * ca.y), std::min(Elo * cb.y, Ehi * cb.y));
+        double ymax = std::max(std::max(Elo * ca.y, Ehi * ca.y), std::max(Elo * cb.y, Ehi * cb.y));
+        {
+          const double pa = std::atan2(ca.y, ca.x), pb = std::atan2(cb.y, cb.x);
+          const double lo = std::min(pa, pb), hi = std::max(pa, pb);
+          for (int k = -2; k <= 2; ++k) {
+            const double ax = k * (0.5 * M_PI);
+            if (ax > lo && ax < hi) {
+              const int kk = (k + 4) & 3;
+              if (kk == 0) xmax = std::max(xmax, Ehi);
+              if (kk == 2) xmin = std::min(xmin, -Ehi);
+              if (kk == 1) ymax = std::max(ymax, Ehi);
+              if (kk == 3) ymin = std::min(ymin, -Ehi);
+            }
+          }
+        }
+        const int Xlo = ((int)std::floor(d.X0[m] + xmin) - 3) & ~3;
+        const int Ylo = (int)std::floor(d.Y0[m] + ymin) - 3;
+        const int W = (((int)std::floor(d.X0[m] + xmax) + 4 - Xlo + 1) + 3) & ~3;
+        const int H = (int)std::floor(d.Y0[m] + ymax) + 4 - Ylo + 1;
+        out[((size_t)m * gy + by) * gx + bx] = make_int4(Xlo, Ylo, W, H);
+      }
+    }
+  }
+  return out;
+}
+
 static size_t cart2lp_lds(const DevPlan& d) {
   const int nft = d.r * (kFRows + 3) - 1;
   return (size_t)(kFPatch + nft * kFQ) * sizeof(float) + (size_t)nft * (sizeof(double2) + sizeof(int2)) +
@@ -336,7 +363,7 @@ rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, 
   rl_status st = ensure_dyn_lds((const void*)k_cart2lp, lds, "hipFuncSetAttribute(k_cart2lp)");
   if (st != RL_OK) return st;
   dim3 grid((d.n_rho + kFQ - 1) / kFQ, (d.n_sup + kFRows - 1) / kFRows, batch * d.m);
-  RL_LAUNCH("k_cart2lp", k_cart2lp, grid, dim3(kThreads), lds, s, d, c, u);
+  RL_LAUNCH("k_cart2lp", k_cart2lp, grid, dim3(kFThreads), lds, s, d, c, u);
   return check_launch("k_cart2lp");
 }
 

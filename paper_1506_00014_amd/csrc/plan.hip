@@ -469,6 +469,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
     for (int k = 0; k <= kPrefR; ++k) pref[k] = (float)(std::sqrt(3.0) * std::pow(z, k));
   }
 
+  const std::vector<int4> fbox = build_fwd_boxes(d, fine_cs, fine_q, erho);
+
   // ---------------- kernel table: zeta_hat on the device in FP64
   const int nkt = g.k_theta / 2 + 1, nkr = g.n_rho / 2 + 1;
   const double P = g.k_theta * d.dtheta;
@@ -505,6 +507,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   const size_t o_er = off; off += al(sizeof(double) * erho.size());
   const size_t o_dt = off; off += al(sizeof(float) * dtap.size());
   const size_t o_ta = off; off += al(sizeof(int2) * (size_t)M * n_own * g.n_s);
+  const size_t o_fb = off; off += al(sizeof(int4) * fbox.size());
   const size_t table_bytes = off;
   // scratch for the quadrature (freed before returning)
   const size_t s_u = 0, s_a = al(sizeof(double) * n_nodes_pad), s_l = 2 * s_a, s_z = 3 * s_a;
@@ -573,6 +576,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
       {o_pf, pref.data(), sizeof(float) * pref.size()},
       {o_er, erho.data(), sizeof(double) * erho.size()},
       {o_dt, dtap.data(), sizeof(float) * dtap.size()},
+      {o_fb, fbox.data(), sizeof(int4) * fbox.size()},
   };
   for (auto& up : ups)
     if ((st = check_hip(hipMemcpy(mem + up.off, up.src, up.bytes, hipMemcpyHostToDevice), "upload table")) != RL_OK)
@@ -589,6 +593,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   d.erho = (const double*)(mem + o_er);
   d.dtap = (const float*)(mem + o_dt);
   d.tau = (const int2*)(mem + o_ta);
+  d.fbox = (const int4*)(mem + o_fb);
   hipLaunchKernelGGL(k_tau_table, dim3(n_own, M), dim3(256), 0, 0, d, (int2*)(mem + o_ta));
   if ((st = check_launch("k_tau_table")) != RL_OK) return cleanup(st);
   if ((st = check_hip(hipDeviceSynchronize(), "k_tau_table")) != RL_OK) return cleanup(st);

@@ -40,6 +40,8 @@ struct DevPlan {
   const int2* tau;         // [m][n_own][n_s] rho position tau of S_m(theta_j, s_k) on each owned
                            // row: (floor(tau) clamped to [-1, n_rho], bits of the FP32 fraction)
   const float* dtap;       // [4r - 1] decimation taps d_n, n = -(2r-1) .. 2r-1
+  const int4* fbox;        // [m][forward block rows][forward block columns] image box of each
+                           // forward block: (x0, y0, width, height), width 0 if no sample in D
   // splat passes of the adjoint (geometry only, built at plan time), see adjoint.hip
   int adj_ntx;             // tiles per image row
   const int* adj_off;      // [tiles + 1] first pass of each tile
@@ -109,6 +111,9 @@ rl_status launch_lp2cart_adj(const rl_plan* p, const float* u, float* cbar, int 
 rl_status launch_ramp(const rl_plan* p, const float* in, float* out, int batch, hipStream_t s);
 rl_status launch_irfft_rows(const rl_plan* p, const float2* spec, float* out, int rows,
                             hipStream_t s);
+// Plan time (host): image boxes of the forward blocks, in the order of the forward grid.
+std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& cs,
+                                  const std::vector<int2>& fq, const std::vector<double>& erho);
 // Plan time: build the adjoint splat passes (allocates plan->d_adj, fills the adj_* fields).
 rl_status build_adj_passes(rl_plan* p);
 // Plan time: raise the LDS limits of the kernels this plan launches (see ensure_dyn_lds).
