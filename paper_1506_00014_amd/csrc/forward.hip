@@ -249,36 +249,51 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const float* _
     }
   }
   __syncthreads();
-  // fine samples: a wave takes one ray (its table entries are wave-uniform LDS broadcasts),
-  // lane l the rho index q0 + l
+  // fine samples: a wave takes one ray at a time (its table entries are wave-uniform LDS
+  // broadcasts), lane l the rho index q0 + l
   const int ql = lane, q = q0 + lane;
   const double E = se[ql];
-  for (int tl = wave; tl < nft; tl += nwave) {
-    const int2 qr = sfq[tl];
-    const double2 tc = scs[tl];
-    float v = 0.f;
-    if (q <= qlast && q >= qr.x && q <= qr.y) {
+  if (staged) {
+    // two rays per step, branch-free (independent chains for the scheduler): taps are clamped
+    // into the patch and samples outside D or past the last ray are zeroed by a select
+    auto sample = [&](int tl) -> float {
+      const int tr = min(tl, nft - 1);
+      const int2 qr = sfq[tr];
+      const double2 tc = scs[tr];
       const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
-      if (staged) {
-        // the 4 x 4 taps start at (kx - 1, ky - 1); the patch holds them (clamped for safety)
-        const double fx = floor(X), fy = floor(Y);
-        float wx[4], wy[4];
-        bspline_w6((float)(X - fx), wx);
-        bspline_w6((float)(Y - fy), wy);
-        const int bx = min(max((int)fx - 1 - Xlo, 0), W - 4);
-        const int by = min(max((int)fy - 1 - Ylo, 0), H - 4);
-        const float* p0 = patch + by * Wp + bx;
+      const double fx = floor(X), fy = floor(Y);
+      float wx[4], wy[4];
+      bspline_w6((float)(X - fx), wx);
+      bspline_w6((float)(Y - fy), wy);
+      const unsigned bx = min((unsigned)((int)fx - 1 - Xlo), (unsigned)(W - 4));
+      const unsigned by = min((unsigned)((int)fy - 1 - Ylo), (unsigned)(H - 4));
+      const float* p0 = patch + __umul24(by, (unsigned)Wp) + bx;
+      float v = 0.f;
 #pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
-          const float* pr = p0 + bb * Wp;
-          v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
-        }
-        v *= 1.0f / 36.0f;
-      } else {
+      for (int bb = 0; bb < 4; ++bb) {
+        const float* pr = p0 + bb * Wp;
+        v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
+      }
+      const bool in = tl < nft && q <= qlast && q >= qr.x && q <= qr.y;
+      return in ? v * (1.0f / 36.0f) : 0.f;
+    };
+    for (int tl = wave; tl < nft; tl += 2 * nwave) {
+      const float v0 = sample(tl);
+      const float v1 = sample(tl + nwave);
+      vbuf[tl * kFQ + ql] = v0;
+      if (tl + nwave < nft) vbuf[(tl + nwave) * kFQ + ql] = v1;
+    }
+  } else {
+    for (int tl = wave; tl < nft; tl += nwave) {
+      const int2 qr = sfq[tl];
+      const double2 tc = scs[tl];
+      float v = 0.f;
+      if (q <= qlast && q >= qr.x && q <= qr.y) {
+        const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
         v = bicubic_at(X, Y, n, [&](int x, int y) { return img[(size_t)wrap1(y, n) * n + wrap1(x, n)]; });
       }
+      vbuf[tl * kFQ + ql] = v;
     }
-    vbuf[tl * kFQ + ql] = v;
   }
   __syncthreads();
   // decimation: u[i][q] = e^rho_q sum_n d_n v[r i + n][q]
