@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
   }
   __syncthreads();
   float2* sh = reinterpret_cast<float2*>(acc);
-  fft_lds<kRowVals, false>(sh, nc, 1, P.tw, P.tw_len);
+  fft_lds<kRowVals, false>(sh, nc, 1, P.twp_rows);
   rfft_post(sh, nc, P.tw, P.tw_len, [&](int k, float2 x) { dst[k] = x; });
 }
 
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void k_irfft_scale(DevPlan P, const float
   const float2* src = spec + row * P.ld;
   irfft_pre(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
   __syncthreads();
-  fft_lds<kRowVals, true>(sh, nc, 1, P.tw, P.tw_len);
+  fft_lds<kRowVals, true>(sh, nc, 1, P.twp_rows);
   const float* x = reinterpret_cast<const float*>(sh);
   float* dst = u + row * P.n_rho;
   for (int q = threadIdx.x; q < P.n_rho; q += blockDim.x) {
@@ -661,7 +661,7 @@ __global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __res
   const float* src = in + row * ns;
   for (int i = threadIdx.x; i < P.lr; i += blockDim.x) xs[i] = i < ns ? src[i] : 0.f;
   __syncthreads();
-  fft_lds<kRowVals, false>(sh, ncr, 1, P.tw, P.tw_len);
+  fft_lds<kRowVals, false>(sh, ncr, 1, P.twp_ramp);
   const int step = P.tw_len / P.lr;
   for (int k = threadIdx.x; k <= ncr / 2; k += blockDim.x) {
     const int km = ncr - k;
@@ -698,7 +698,7 @@ __global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __res
     }
   }
   __syncthreads();
-  fft_lds<kRowVals, true>(sh, ncr, 1, P.tw, P.tw_len);
+  fft_lds<kRowVals, true>(sh, ncr, 1, P.twp_ramp);
   float* dst = out + row * ns;
   for (int i = threadIdx.x; i < ns; i += blockDim.x) dst[i] = xs[i];
 }

@@ -66,15 +66,22 @@ __device__ __forceinline__ void dft(float2* v) {
   else dft8<INV>(v);
 }
 
+// Twiddles of the Stockham passes, laid out per pass (built with the plan): the pass of
+// radix R after sub-transforms of length Ns holds, for k = 0 .. Ns - 1, the R - 1 twiddles
+// exp(-2 pi i r k / (R Ns)), r = 1 .. R - 1, padded to an even count (RP entries), so that
+// a butterfly reads its twiddles as consecutive 16-byte loads.
+__host__ __device__ constexpr int stockham_radix(int left) { return left >= 8 ? 8 : (left == 4 ? 4 : 2); }
+__host__ __device__ constexpr int stockham_slots(int R) { return R == 8 ? 8 : (R == 4 ? 4 : 2); }
+
 // One Stockham pass of radix R over nfft independent FFTs of length N stored back to back
-// in LDS (buf[f*N + i]).  Ns is the length of the sub-transforms already done.  Every thread
-// of the block must call it (it contains barriers).  MAXB bounds the butterflies per thread.
+// in LDS (buf[f*N + i]).  Ns is the length of the sub-transforms already done; twp points at
+// this pass's twiddles.  Every thread of the block must call it (it contains barriers).
+// MAXB bounds the butterflies per thread.
 template <int R, int MAXB, bool INV>
-__device__ __forceinline__ void stockham_pass(float2* buf, int N, int nfft, int Ns,
-                                              const float2* __restrict__ tw, int tw_len) {
+__device__ __forceinline__ void stockham_pass(float2* buf, int N, int nfft, int Ns, const float2* __restrict__ twp) {
+  constexpr int RP = stockham_slots(R);
   const int nbf = N / R;
   const int total = nbf * nfft;
-  const int step = tw_len / (R * Ns);
   float2 v[MAXB][R];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
@@ -84,13 +91,21 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int N, int nfft, int 
       const int j = id - f * nbf;
       const int k = j & (Ns - 1);
       const float2* base = buf + f * N;
+      float2 w[RP];
+      const float4* tq = reinterpret_cast<const float4*>(twp + k * RP);
+#pragma unroll
+      for (int i = 0; i < RP / 2; ++i) {
+        const float4 t = tq[i];
+        w[2 * i] = make_float2(t.x, t.y);
+        w[2 * i + 1] = make_float2(t.z, t.w);
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         float2 x = base[j + r * nbf];
         if (r > 0) {
-          float2 w = tw[r * k * step];
-          if (INV) w.y = -w.y;
-          x = cmul(x, w);
+          float2 tw = w[r - 1];
+          if (INV) tw.y = -tw.y;
+          x = cmul(x, tw);
         }
         v[b][r] = x;
       }
@@ -115,24 +130,19 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int N, int nfft, int 
 }
 
 // Unnormalised in-place FFT (forward: exp(-2 pi i jk/N); INV: exp(+...)) of nfft
-// transforms of power-of-two length N >= 2 held in LDS.  MAXV bounds the complex values
-// per thread: nfft * N <= MAXV * blockDim.x.  Callers synchronise before the call.
+// transforms of power-of-two length N >= 2 held in LDS; twp is the pass twiddle table of
+// length N.  MAXV bounds the complex values per thread: nfft * N <= MAXV * blockDim.x.
+// Callers synchronise before the call.
 template <int MAXV, bool INV>
-__device__ __forceinline__ void fft_lds(float2* buf, int N, int nfft, const float2* __restrict__ tw,
-                                        int tw_len) {
+__device__ __forceinline__ void fft_lds(float2* buf, int N, int nfft, const float2* __restrict__ twp) {
   int Ns = 1;
   while (Ns < N) {
-    const int left = N / Ns;
-    if (left >= 8) {
-      stockham_pass<8, MAXV / 8, INV>(buf, N, nfft, Ns, tw, tw_len);
-      Ns *= 8;
-    } else if (left == 4) {
-      stockham_pass<4, MAXV / 4, INV>(buf, N, nfft, Ns, tw, tw_len);
-      Ns *= 4;
-    } else {
-      stockham_pass<2, MAXV / 2, INV>(buf, N, nfft, Ns, tw, tw_len);
-      Ns *= 2;
-    }
+    const int R = stockham_radix(N / Ns);
+    if (R == 8) stockham_pass<8, MAXV / 8, INV>(buf, N, nfft, Ns, twp);
+    else if (R == 4) stockham_pass<4, MAXV / 4, INV>(buf, N, nfft, Ns, twp);
+    else stockham_pass<2, MAXV / 2, INV>(buf, N, nfft, Ns, twp);
+    twp += Ns * stockham_slots(R);
+    Ns *= R;
   }
 }
 

@@ -392,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void k_rfft_rows(DevPlan P, const float* 
   const float2* src = reinterpret_cast<const float2*>(in + row * P.n_rho);
   for (int i = threadIdx.x; i < nc; i += blockDim.x) sh[i] = src[i];
   __syncthreads();
-  fft_lds<kRowVals, false>(sh, nc, 1, P.tw, P.tw_len);
+  fft_lds<kRowVals, false>(sh, nc, 1, P.twp_rows);
   float2* dst = out + row * P.ld;
   rfft_post(sh, nc, P.tw, P.tw_len, [&](int k, float2 x) { dst[k] = x; });
 }
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void k_irfft_rows(DevPlan P, const float2
   const float2* src = in + row * P.ld;
   irfft_pre(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
   __syncthreads();
-  fft_lds<kRowVals, true>(sh, nc, 1, P.tw, P.tw_len);
+  fft_lds<kRowVals, true>(sh, nc, 1, P.twp_rows);
   float2* dst = reinterpret_cast<float2*>(out + row * P.n_rho);
   for (int i = threadIdx.x; i < nc; i += blockDim.x) dst[i] = sh[i];
 }
@@ -445,7 +445,6 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
   const int lid = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int bm = lid / gridDim.x;
   const int col0 = (lid - bm * gridDim.x) * cw;
-  const int tw_step = P.tw_len / K;
   const float2* src = in + (size_t)bm * in_rows * P.ld;
   // stage A
   {
@@ -460,10 +459,13 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
       }
       reg_fft<K1, false>(x, P.tw, P.tw_len);
       float2* T = sh + c * CS;
+      const float4* tq = reinterpret_cast<const float4*>(P.tw_theta + (size_t)n2 * K1);
 #pragma unroll
-      for (int k1 = 0; k1 < K1; ++k1) {
-        const float2 v = (k1 == 0 || n2 == 0) ? x[k1] : cmul(x[k1], P.tw[(n2 * k1) * tw_step]);
-        T[k1 * RS + n2] = v;
+      for (int k1 = 0; k1 < K1; k1 += 2) {
+        const float4 t = tq[k1 / 2];
+        const float2 w0 = make_float2(t.x, t.y), w1 = make_float2(t.z, t.w);
+        T[k1 * RS + n2] = (k1 == 0 || n2 == 0) ? x[k1] : cmul(x[k1], w0);
+        T[(k1 + 1) * RS + n2] = n2 == 0 ? x[k1 + 1] : cmul(x[k1 + 1], w1);
       }
     }
   }
@@ -498,16 +500,15 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
     const int col = col0 + c;
     if (n2 < K2 && col < ncol) {
       const float2* T = sh + c * CS;
+      const float4* tq = reinterpret_cast<const float4*>(P.tw_theta + (size_t)n2 * K1);
       float2 x[K1];
 #pragma unroll
-      for (int k1 = 0; k1 < K1; ++k1) {
-        float2 v = T[k1 * RS + n2];
-        if (k1 != 0 && n2 != 0) {
-          float2 w = P.tw[(n2 * k1) * tw_step];
-          w.y = -w.y;
-          v = cmul(v, w);
-        }
-        x[k1] = v;
+      for (int k1 = 0; k1 < K1; k1 += 2) {
+        const float4 t = tq[k1 / 2];
+        const float2 w0 = make_float2(t.x, -t.y), w1 = make_float2(t.z, -t.w);
+        const float2 v0 = T[k1 * RS + n2], v1 = T[(k1 + 1) * RS + n2];
+        x[k1] = (k1 == 0 || n2 == 0) ? v0 : cmul(v0, w0);
+        x[k1 + 1] = n2 == 0 ? v1 : cmul(v1, w1);
       }
       reg_fft<K1, true>(x, P.tw, P.tw_len);
       float2* dst = out + (size_t)bm * out_rows * P.ld;
@@ -597,7 +598,7 @@ __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2
   const float2* src = spec + ((size_t)bm * P.n_own + o) * P.ld;
   irfft_pre(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
   __syncthreads();
-  fft_lds<kRowVals, true>(sh, nc, 1, P.tw, P.tw_len);
+  fft_lds<kRowVals, true>(sh, nc, 1, P.twp_rows);
   const float* x = reinterpret_cast<const float*>(sh);
   const float inv_aR = (float)(1.0 / (6.0 * P.a_R));  // 1/a_R and the weights' 1/6
   float* dst = sino + ((size_t)b * P.n_theta + j) * P.n_s;

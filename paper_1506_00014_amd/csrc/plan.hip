@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "fft_device.h"
 #include "rl_internal.h"
 
 namespace rl {
@@ -441,6 +442,24 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
     const double a = -2.0 * M_PI * (double)i / d.tw_len;
     tw[i] = make_float2((float)std::cos(a), (float)std::sin(a));
   }
+  // Stockham pass twiddles (entries of tw, so the passes multiply by the same values)
+  auto pass_twiddles = [&](int N) {
+    std::vector<float2> out;
+    for (int Ns = 1; Ns < N;) {
+      const int R = stockham_radix(N / Ns), RP = stockham_slots(R), step = d.tw_len / (R * Ns);
+      for (int k = 0; k < Ns; ++k)
+        for (int r = 1; r <= RP; ++r) out.push_back(r < R ? tw[(size_t)r * k * step] : make_float2(0.f, 0.f));
+      Ns *= R;
+    }
+    return out;
+  };
+  const std::vector<float2> twp_rows = pass_twiddles(d.nc), twp_ramp = pass_twiddles(d.lr / 2);
+  std::vector<float2> tw_theta(g.k_theta);
+  {
+    const int K1 = theta_k1(g.k_theta), K2 = g.k_theta / K1, step = d.tw_len / g.k_theta;
+    for (int n2 = 0; n2 < K2; ++n2)
+      for (int k1 = 0; k1 < K1; ++k1) tw_theta[(size_t)n2 * K1 + k1] = tw[(size_t)n2 * k1 * step];
+  }
   // Ram-Lak kernel (times ds) on a cyclic grid of length lr, and its DFT / lr (real, even)
   std::vector<float> ramp(d.lr / 2 + 1);
   {
@@ -502,6 +521,9 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   const size_t o_oj = off; off += al(sizeof(int) * own_j.size());
   const size_t o_oc = off; off += al(sizeof(double) * own_cos.size());
   const size_t o_tw = off; off += al(sizeof(float2) * tw.size());
+  const size_t o_tpr = off; off += al(sizeof(float2) * twp_rows.size());
+  const size_t o_tpl = off; off += al(sizeof(float2) * twp_ramp.size());
+  const size_t o_tth = off; off += al(sizeof(float2) * tw_theta.size());
   const size_t o_rp = off; off += al(sizeof(float) * ramp.size());
   const size_t o_pf = off; off += al(sizeof(float) * pref.size());
   const size_t o_er = off; off += al(sizeof(double) * erho.size());
@@ -572,6 +594,9 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
       {o_oj, own_j.data(), sizeof(int) * own_j.size()},
       {o_oc, own_cos.data(), sizeof(double) * own_cos.size()},
       {o_tw, tw.data(), sizeof(float2) * tw.size()},
+      {o_tpr, twp_rows.data(), sizeof(float2) * twp_rows.size()},
+      {o_tpl, twp_ramp.data(), sizeof(float2) * twp_ramp.size()},
+      {o_tth, tw_theta.data(), sizeof(float2) * tw_theta.size()},
       {o_rp, ramp.data(), sizeof(float) * ramp.size()},
       {o_pf, pref.data(), sizeof(float) * pref.size()},
       {o_er, erho.data(), sizeof(double) * erho.size()},
@@ -588,6 +613,9 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   d.own_j = (const int*)(mem + o_oj);
   d.own_cos = (const double*)(mem + o_oc);
   d.tw = (const float2*)(mem + o_tw);
+  d.twp_rows = (const float2*)(mem + o_tpr);
+  d.twp_ramp = (const float2*)(mem + o_tpl);
+  d.tw_theta = (const float2*)(mem + o_tth);
   d.ramp = (const float*)(mem + o_rp);
   d.pref = (const float*)(mem + o_pf);
   d.erho = (const double*)(mem + o_er);

@@ -34,6 +34,10 @@ struct DevPlan {
   const int* own_j;        // [m][n_own] sinogram row, bit 30 set for wrapped rows, -1 if none
   const double* own_cos;   // [m][n_own] cos(theta'_j)
   const float2* tw;        // [tw_len] exp(-2 pi i n / tw_len)
+  const float2* twp_rows;  // Stockham pass twiddles of length nc (rho rows), see fft_device.h
+  const float2* twp_ramp;  // Stockham pass twiddles of length lr / 2 (ramp filter rows)
+  const float2* tw_theta;  // [k_theta] four-step twiddles exp(-2 pi i n2 k1 / k_theta) at
+                           // n2 * K1 + k1 (K1 x K2 = k_theta as the theta pass splits it)
   const float* ramp;       // [lr/2 + 1] ramp multiplier (real), includes 1/lr
   const float* pref;       // [kPrefR + 1] prefilter taps sqrt(3) z^|k|
   const double* erho;      // [n_rho] e^{rho_q} / (a_R dx): image-index length of the ray at rho_q
@@ -111,6 +115,8 @@ rl_status launch_lp2cart_adj(const rl_plan* p, const float* u, float* cbar, int 
 rl_status launch_ramp(const rl_plan* p, const float* in, float* out, int batch, hipStream_t s);
 rl_status launch_irfft_rows(const rl_plan* p, const float2* spec, float* out, int rows,
                             hipStream_t s);
+// The theta pass splits k_theta = K1 K2 (four-step FFT); K1 as a function of k_theta.
+constexpr int theta_k1(int k_theta) { return k_theta <= 32 ? k_theta : 32; }
 // Plan time (host): image boxes of the forward blocks, in the order of the forward grid.
 std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& cs,
                                   const std::vector<int2>& fq, const std::vector<double>& erho);
