@@ -92,17 +92,19 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int N, int nfft, int 
       const int k = j & (Ns - 1);
       const float2* base = buf + f * N;
       float2 w[RP];
-      const float4* tq = reinterpret_cast<const float4*>(twp + k * RP);
+      if (Ns > 1) {  // uniform; the first pass multiplies by exp(0) = 1
+        const float4* tq = reinterpret_cast<const float4*>(twp + k * RP);
 #pragma unroll
-      for (int i = 0; i < RP / 2; ++i) {
-        const float4 t = tq[i];
-        w[2 * i] = make_float2(t.x, t.y);
-        w[2 * i + 1] = make_float2(t.z, t.w);
+        for (int i = 0; i < RP / 2; ++i) {
+          const float4 t = tq[i];
+          w[2 * i] = make_float2(t.x, t.y);
+          w[2 * i + 1] = make_float2(t.z, t.w);
+        }
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         float2 x = base[j + r * nbf];
-        if (r > 0) {
+        if (r > 0 && Ns > 1) {
           float2 tw = w[r - 1];
           if (INV) tw.y = -tw.y;
           x = cmul(x, tw);

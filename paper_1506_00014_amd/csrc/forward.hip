@@ -18,96 +18,117 @@
 namespace rl {
 
 // ------------------------------------------------------------------ prefilter
-constexpr int kPT = 64;                // output tile side
-constexpr int kPI = kPT + 2 * kPrefR;  // input tile side (96)
+constexpr int kPSW = 64;                   // output columns per block
+constexpr int kPSI = kPSW + 2 * kPrefR;    // input columns per block (96)
+constexpr int kPRB = 32;                   // rows per step
+constexpr int kPSeg = 512;                 // output rows per block
+constexpr int kPRing = kPRB + 2 * kPrefR;  // row-filtered rows kept (64, a power of two)
+constexpr int kPGroups = kPRB * kPSI / 4;  // float4 groups of input per step (768)
+static_assert(kPGroups % kThreads == 0, "whole groups per thread");
 
-// Block: one kPT x kPT output tile.  The (kPT + 32)^2 input tile (periodic wrap) is staged in
-// LDS; the row pass filters all kPI rows into kPT columns, the column pass the kPT columns;
-// each thread filters a run of outputs from a register window.
+// Block: a strip of kPSW columns and up to kPSeg rows of one slice, streamed down in steps
+// of kPRB rows.  A step row-filters kPRB new input rows (the periodic 2 kPrefR + 1 taps,
+// input staged in LDS) into a ring of the last kPRing row-filtered rows, then column-filters
+// the kPRB output rows whose taps the ring now holds.  The first step only fills the ring.
+// The next step's input is loaded into registers while the current step computes.
 __global__ __launch_bounds__(kThreads) void k_prefilter(const float* __restrict__ in, float* __restrict__ out,
                                                         int n, float scale, const float* __restrict__ pref) {
-  __shared__ float tin[kPI][kPI + 1];
-  __shared__ float trow[kPI][kPT + 1];
+  __shared__ float tin[kPRB][kPSI + 1];
+  __shared__ float ring[kPRing][kPSW + 1];
   __shared__ float q[kPrefR + 1];
   const int b = blockIdx.z;
-  const int ty0 = blockIdx.y * kPT, tx0 = blockIdx.x * kPT;
+  const int x0 = blockIdx.x * kPSW;
+  const int yseg0 = blockIdx.y * kPSeg, yseg1 = min(yseg0 + kPSeg, n);
+  const int base = yseg0 - kPrefR;  // row-filtered row y sits in ring slot (y - base) % kPRing
   const float* src = in + (size_t)b * n * n;
+  float* dst = out + (size_t)b * n * n;
   if (threadIdx.x <= kPrefR) q[threadIdx.x] = pref[threadIdx.x];
-  {
-    // flat element order, (ly, lx) stepped by the block stride; 4 loads in flight per thread
-    constexpr int tot = kPI * kPI;
-    constexpr int dly = kThreads / kPI, dlx = kThreads - dly * kPI;
-    int ly = (int)threadIdx.x / kPI, lx = (int)threadIdx.x - ly * kPI;
-    for (int base = 0; base < tot; base += 4 * kThreads) {
-      float v[4];
-      int dl[4];
+  const bool vec_ok = (n & 3) == 0 && x0 - kPrefR >= 0 && x0 - kPrefR + kPSI <= n;  // uniform
+  // input rows [ry, ry + kPRB) x columns [x0 - kPrefR, x0 - kPrefR + kPSI), periodic
+  auto load = [&](int ry, float4* v) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int idx = base + u * kThreads + (int)threadIdx.x;
-        dl[u] = -1;
-        if (idx < tot) {
-          int gy = ty0 - kPrefR + ly, gx = tx0 - kPrefR + lx;
-          if (gy < 0 || gy >= n) gy = ((gy % n) + n) % n;
-          if (gx < 0 || gx >= n) gx = ((gx % n) + n) % n;
-          v[u] = src[(size_t)gy * n + gx];
-          dl[u] = ly * (kPI + 1) + lx;
+    for (int u = 0; u < kPGroups / kThreads; ++u) {
+      const int g = (int)threadIdx.x + u * kThreads;
+      const int ly = g / (kPSI / 4), lg = g - ly * (kPSI / 4);
+      int gy = ry + ly;
+      if (gy < 0 || gy >= n) gy = ((gy % n) + n) % n;
+      const float* srow = src + (size_t)gy * n;
+      const int gx = x0 - kPrefR + 4 * lg;
+      if (vec_ok) {
+        v[u] = *reinterpret_cast<const float4*>(srow + gx);
+      } else {
+        float t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int x = gx + e;
+          if (x < 0 || x >= n) x = ((x % n) + n) % n;
+          t[e] = srow[x];
         }
-        ly += dly;
-        lx += dlx;
-        if (lx >= kPI) {
-          lx -= kPI;
-          ++ly;
-        }
+        v[u] = make_float4(t[0], t[1], t[2], t[3]);
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (dl[u] >= 0) (&tin[0][0])[dl[u]] = v[u];
     }
-  }
+  };
+  float4 v[kPGroups / kThreads];
+  load(yseg0 - kPRB + kPrefR, v);  // input rows of the first step
   __syncthreads();
   float qk[kPrefR + 1];
 #pragma unroll
   for (int k = 0; k <= kPrefR; ++k) qk[k] = q[k];
-  // rows: kPI rows x (kPT / 8) runs of 8 outputs = 768 runs, 3 per thread
-  {
-    constexpr int R = 8, runs = kPI * (kPT / R);
-    for (int rid = threadIdx.x; rid < runs; rid += kThreads) {
-      const int row = rid / (kPT / R), seg = rid % (kPT / R);
+  // step at cy computes row-filtered rows [cy + kPrefR, cy + kPrefR + kPRB) and outputs rows
+  // [cy, cy + kPRB); the first step (cy = yseg0 - kPRB) only fills the ring
+  for (int cy = yseg0 - kPRB; cy < yseg1; cy += kPRB) {
+#pragma unroll
+    for (int u = 0; u < kPGroups / kThreads; ++u) {
+      const int g = (int)threadIdx.x + u * kThreads;
+      const int ly = g / (kPSI / 4), lg = g - ly * (kPSI / 4);
+      float* d = &tin[ly][4 * lg];
+      d[0] = v[u].x;
+      d[1] = v[u].y;
+      d[2] = v[u].z;
+      d[3] = v[u].w;
+    }
+    __syncthreads();
+    if (cy + kPRB < yseg1) load(cy + kPRB + kPrefR, v);  // next step's input, in flight
+    {
+      // rows: kPRB rows x (kPSW / 8) runs of 8 outputs, one run per thread
+      constexpr int R = 8;
+      const int row = threadIdx.x / (kPSW / R), seg = threadIdx.x % (kPSW / R);
       float x[R + 2 * kPrefR];
 #pragma unroll
       for (int i = 0; i < R + 2 * kPrefR; ++i) x[i] = tin[row][seg * R + i];
+      float* rr = ring[(cy + kPrefR + row - base) & (kPRing - 1)];
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         float acc = qk[0] * x[j + kPrefR];
 #pragma unroll
         for (int k = 1; k <= kPrefR; ++k) acc += qk[k] * (x[j + kPrefR - k] + x[j + kPrefR + k]);
-        trow[row][seg * R + j] = acc;
+        rr[seg * R + j] = acc;
       }
     }
-  }
-  __syncthreads();
-  // columns: kPT columns x 4 runs of 16 outputs, one run per thread
-  float* dst = out + (size_t)b * n * n;
-  {
-    constexpr int R = kPT / (kThreads / kPT);  // 16
-    const int col = threadIdx.x % kPT, seg = threadIdx.x / kPT;
-    float y[R + 2 * kPrefR];
+    __syncthreads();
+    if (cy >= yseg0) {  // uniform
+      // columns: kPSW columns x (kPRB / 8) runs of 8 outputs, one run per thread
+      constexpr int R = kPRB / (kThreads / kPSW);  // 8
+      const int col = threadIdx.x % kPSW, run = threadIdx.x / kPSW;
+      const int y0 = cy + run * R;
+      float y[R + 2 * kPrefR];
 #pragma unroll
-    for (int i = 0; i < R + 2 * kPrefR; ++i) y[i] = trow[seg * R + i][col];
+      for (int i = 0; i < R + 2 * kPrefR; ++i) y[i] = ring[(y0 - kPrefR + i - base) & (kPRing - 1)][col];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      float acc = qk[0] * y[j + kPrefR];
+      for (int j = 0; j < R; ++j) {
+        float acc = qk[0] * y[j + kPrefR];
 #pragma unroll
-      for (int k = 1; k <= kPrefR; ++k) acc += qk[k] * (y[j + kPrefR - k] + y[j + kPrefR + k]);
-      const int gy = ty0 + seg * R + j, gx = tx0 + col;
-      if (gy < n && gx < n) dst[(size_t)gy * n + gx] = acc * scale;
+        for (int k = 1; k <= kPrefR; ++k) acc += qk[k] * (y[j + kPrefR - k] + y[j + kPrefR + k]);
+        const int gy = y0 + j, gx = x0 + col;
+        if (gy < yseg1 && gx < n) dst[(size_t)gy * n + gx] = acc * scale;
+      }
     }
   }
 }
 
 rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int batch, float scale, hipStream_t s) {
   const int n = p->d.n;
-  dim3 grid((n + kPT - 1) / kPT, (n + kPT - 1) / kPT, batch);
+  dim3 grid((n + kPSW - 1) / kPSW, (n + kPSeg - 1) / kPSeg, batch);
   RL_LAUNCH("k_prefilter", k_prefilter, grid, dim3(kThreads), 0, s, in, out, n, scale, p->d.pref);
   return check_launch("k_prefilter");
 }
