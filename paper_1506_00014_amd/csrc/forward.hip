@@ -452,7 +452,8 @@ rl_status launch_irfft_rows(const rl_plan* p, const float2* in, float* out, int 
 //   B   thread (k1, c): K2-point FFT over n2 (-> k = k1 + K1 k2); times H (or conj H);
 //       inverse K2-point FFT -> LDS
 //   A'  thread (n2, c): times W_K^{-n2 k1}; inverse K1-point FFT -> out rows K2 n1 + n2
-// Rows outside the input range are zero; only the requested output rows are written.
+// Rows outside the input range are zero; only the requested output rows are written.  The
+// twiddles W_K^{n2 k1} are copied to LDS once per block (n2-major, as stage A reads them).
 template <int K1, int K2>
 __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2* __restrict__ in, int in_rows,
                                                          int in_off, float2* __restrict__ out, int out_rows,
@@ -462,6 +463,13 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
   constexpr int RS = K2 + 1;           // padded stride between k1 rows
   constexpr int CS = K1 * RS + 1;      // padded stride between columns
   const int nkt = K / 2 + 1, ncol = P.nc + 1;
+  // the four-step twiddles W_K^{n2 k1}, copied once per block behind the columns' buffers
+  float2* twl = sh + ((cw * CS + 1) & ~1);
+  {
+    const float4* src4 = reinterpret_cast<const float4*>(P.tw_theta);
+    float4* dst4 = reinterpret_cast<float4*>(twl);
+    for (int i = threadIdx.x; i < K / 2; i += blockDim.x) dst4[i] = src4[i];
+  }
   // neighbouring column strips share 128-byte lines: keep them on one XCD
   const int lid = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int bm = lid / gridDim.x;
@@ -471,16 +479,20 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
   {
     const int c = threadIdx.x % cw, n2 = threadIdx.x / cw;
     const int col = col0 + c;
-    if (n2 < K2 && col < ncol) {
-      float2 x[K1];
+    const bool act = n2 < K2 && col < ncol;
+    float2 x[K1];
+    if (act) {
 #pragma unroll
       for (int n1 = 0; n1 < K1; ++n1) {
         const int ir = K2 * n1 + n2 - in_off;
         x[n1] = (ir >= 0 && ir < in_rows) ? src[(size_t)ir * P.ld + col] : make_float2(0.f, 0.f);
       }
       reg_fft<K1, false>(x, P.tw, P.tw_len);
+    }
+    __syncthreads();  // the twiddle copy is complete
+    if (act) {
       float2* T = sh + c * CS;
-      const float4* tq = reinterpret_cast<const float4*>(P.tw_theta + (size_t)n2 * K1);
+      const float4* tq = reinterpret_cast<const float4*>(twl + n2 * K1);
 #pragma unroll
       for (int k1 = 0; k1 < K1; k1 += 2) {
         const float4 t = tq[k1 / 2];
@@ -521,7 +533,7 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
     const int col = col0 + c;
     if (n2 < K2 && col < ncol) {
       const float2* T = sh + c * CS;
-      const float4* tq = reinterpret_cast<const float4*>(P.tw_theta + (size_t)n2 * K1);
+      const float4* tq = reinterpret_cast<const float4*>(twl + n2 * K1);
       float2 x[K1];
 #pragma unroll
       for (int k1 = 0; k1 < K1; k1 += 2) {
@@ -549,7 +561,7 @@ static int theta_cw() {
 
 template <int K1, int K2>
 static size_t theta_lds() {
-  return (size_t)theta_cw<K1, K2>() * (K1 * (K2 + 1) + 1) * sizeof(float2);
+  return ((size_t)theta_cw<K1, K2>() * (K1 * (K2 + 1) + 1) + 1 + K1 * K2) * sizeof(float2);
 }
 
 template <int K1, int K2>
