@@ -126,11 +126,12 @@ __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : 
 // rho indices (intersected with the ray's range inside D), which is then trimmed at both
 // ends to exactly the samples whose 4 x 4 bicubic footprint meets the tile (the footprint
 // origin floor(X) moves monotonically along a ray, so those samples are contiguous).  The
-// ranges are cut into segments, long enough that every thread walks at most one, and
-// numbered by a scan with the rays taken kRayGap apart (rays t, t + kRayGap, ... first), so
-// that the threads of a wave, which walk consecutive segments in lockstep, sit on rays
-// kRayGap apart or a segment length apart on one ray: their footprints are then mostly disjoint and each LDS add of a wave
-// spreads over the banks.  Each sample is rebuilt from the coarse rows by the transposed
+// ranges are cut into segments of one length (and a shorter last one per ray), long enough
+// that every thread walks at most one, and numbered by a scan with the rays taken kRayGap
+// apart (rays t, t + kRayGap, ... first), full segments before the shorter ones, so that
+// the threads of a wave, which walk consecutive segments in lockstep, mostly have equal
+// work and sit on rays kRayGap apart or a segment length apart on one ray: their footprints
+// are then mostly disjoint and each LDS add of a wave spreads over the banks.  Each sample is rebuilt from the coarse rows by the transposed
 // decimation filter; its 16 weighted values are summed in registers into the walking
 // thread's 4 x 4 footprint.  Along a ray the footprint origin floor(X), floor(Y) advances by
 // at most one pixel per sample for the usual geometries, so the footprint is kept oriented
@@ -287,8 +288,9 @@ __device__ __forceinline__ void splat_walk(const SegWalk& sw, double* acc, const
 // A pass is one partition m, one periodic shift (sx, sy) of one tile and up to kARows fine
 // rays ta .. ta + nrows - 1, laid out in ray slots (slot of ray k: (k % kRayGap) * ng +
 // k / kRayGap, ng = ceil(nrows / kRayGap); slots past the last ray are empty).  Header, three
-// int4: (m, sx, sy, nslot), (cg0, cg1, qlo, qhi), (seglen, segments, first slot record, 0);
-// one int4 per slot: (t, first rho index, last rho index, first segment).  The kernel below
+// int4: (m, sx, sy, nslot), (cg0, cg1, qlo, qhi), (seglen, segments, first slot record, full
+// segments); one int4 per slot: (t, first rho index, last rho index, first full segment |
+// first shorter segment << 16).  The kernel below
 // computes them (one block per tile): COUNT only counts passes and slots per tile, WRITE
 // stores them at the offsets the host derives from the counts.
 constexpr int kBThreads = 256;  // threads of the pass builder (>= kASlots)
@@ -300,7 +302,8 @@ __global__ __launch_bounds__(kBThreads) void k_adj_build(DevPlan P, int2* __rest
   __shared__ int rq0[kASlots];
   __shared__ int rqb[kASlots];
   __shared__ int rpre[kASlots + 1];
-  __shared__ int qext[3];
+  __shared__ int rpart[kASlots + 1];
+  __shared__ int qext[4];
   const int n = P.n, r = P.r;
   const int tile = blockIdx.y * gridDim.x + blockIdx.x;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
@@ -410,15 +413,25 @@ __global__ __launch_bounds__(kBThreads) void k_adj_build(DevPlan P, int2* __rest
               nray += __shfl_xor(nray, off, 64);
             }
             const int len = max(kSegMin, (ssum + (kAThreads - nray) - 1) / (kAThreads - nray));
-            for (int i = threadIdx.x; i < nslot; i += 64) rpre[i] = (rpre[i] + len - 1) / len;
-            const int total = wave_exclusive_scan(rpre, nslot);
+            // a ray's range is cut into full segments of len samples and at most one shorter
+            // one; the full segments of all rays are numbered first, so that the waves that
+            // walk them have no idle lanes
+            for (int i = threadIdx.x; i < nslot; i += 64) {
+              const int c = rpre[i];
+              rpre[i] = c / len;
+              rpart[i] = (c % len) != 0;
+            }
+            const int nfull = wave_exclusive_scan(rpre, nslot);
+            const int npart = wave_exclusive_scan(rpart, nslot);
             if (threadIdx.x == 0) {
-              rpre[nslot] = total;
+              rpre[nslot] = nfull;
+              rpart[nslot] = npart;
               qext[2] = len;
+              qext[3] = nfull;
             }
           }
           __syncthreads();
-          const int total = rpre[nslot];
+          const int total = rpre[nslot] + rpart[nslot];
           if (total > 0) {  // uniform
             if (WRITE) {
               const int cg0 = max(floordiv(tc, r) - 1, 0);
@@ -427,11 +440,12 @@ __global__ __launch_bounds__(kBThreads) void k_adj_build(DevPlan P, int2* __rest
                 int4* h = passes + 3 * (size_t)(pass0 + npass);
                 h[0] = make_int4(m, sx, sy, nslot);
                 h[1] = make_int4(cg0, cg1, qext[0], qext[1]);
-                h[2] = make_int4(qext[2], total, rec0 + nrec, 0);
+                h[2] = make_int4(qext[2], total, rec0 + nrec, qext[3]);
               }
               for (int sl = threadIdx.x; sl < nslot; sl += blockDim.x) {
                 const int k = (sl % ng) * kRayGap + sl / ng;
-                rays[rec0 + nrec + sl] = make_int4(tc + min(k, nrows - 1), rq0[sl], rqb[sl], rpre[sl]);
+                rays[rec0 + nrec + sl] =
+                    make_int4(tc + min(k, nrows - 1), rq0[sl], rqb[sl], rpre[sl] | (rpart[sl] << 16));
               }
             }
             ++npass;
@@ -519,7 +533,8 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
   // FP64: LDS float atomics are slow on this target.
   __shared__ double acc[kAW * kAP];
   __shared__ int rq0[kASlots];
-  __shared__ int rpre[kASlots + 1];
+  __shared__ int rpre[kASlots + 1];   // first full segment of each slot
+  __shared__ int rppre[kASlots + 1];  // first shorter segment of each slot
   __shared__ int rcnt[kASlots];
   __shared__ int rcg[kASlots];
   __shared__ float4 rdw[kASlots];
@@ -539,7 +554,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
     const int ux0 = tx0 + h0.y * n, ux1 = txe + h0.y * n;
     const int uy0 = ty0 + h0.z * n, uy1 = tye + h0.z * n;
     const int cg0 = h1.x, cg1 = h1.y, qlo = h1.z, qhi = h1.w;
-    const int seglen = h2.x, total = h2.y;
+    const int seglen = h2.x, total = h2.y, nfull = h2.w;
     const int4* rec = P.adj_ray + h2.z;
     const double2* cs = P.fine_cs + (size_t)m * P.n_fine;
     const float* Ub = U + (size_t)(b * P.m + m) * P.n_sup * P.n_rho;
@@ -550,12 +565,16 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
       const int cg = floordiv(e.x, r);
       rq0[sl] = e.y;
       rcnt[sl] = e.z;
-      rpre[sl] = e.w;
+      rpre[sl] = e.w & 0xffff;
+      rppre[sl] = e.w >> 16;
       rcs[sl] = cs[e.x - P.t_min];
       rcg[sl] = cg;
       rdw[sl] = P.dec[e.x - r * cg];
     }
-    if (threadIdx.x == 0) rpre[nslot] = total;
+    if (threadIdx.x == 0) {
+      rpre[nslot] = nfull;
+      rppre[nslot] = total - nfull;
+    }
     // rho windows of the row copies; a window starts at a multiple of 4 and spans a multiple
     // of 4, so rows are copied as float4 (n_rho is a power of two)
     const int nur = cg1 - cg0 + 1;
@@ -596,11 +615,14 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
       __syncthreads();
       // walk whole segments (clipped to the window)
       for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        // the slot holding segment idx: the last k with rpre[k] <= idx
+        // segments [0, nfull) are full ones, the rest the shorter last ones of their rays;
+        // the slot holding segment j of its kind: the last k with prefix[k] <= j
+        const bool full = idx < nfull;
+        const int j = full ? idx : idx - nfull;
         int lo = 0, hi = nslot - 1;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
-          if (rpre[mid] <= idx) lo = mid;
+          if ((full ? rpre[mid] : rppre[mid]) <= j) lo = mid;
           else hi = mid - 1;
         }
         const int k = lo;
@@ -610,7 +632,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
         const double2 tcs = rcs[k];
         sw.cx = tcs.x;
         sw.cy = tcs.y;
-        const int q0 = rq0[k] + (idx - rpre[k]) * seglen;
+        const int q0 = rq0[k] + (full ? j - rpre[k] : rpre[k + 1] - rpre[k]) * seglen;
         sw.qbeg = max(q0, wq);
         sw.qend = min(min(q0 + seglen - 1, rcnt[k]), wend);
         sw.ux0 = ux0;
