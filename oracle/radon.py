@@ -38,7 +38,9 @@ bspline.py and kernel.py):
   * W (eq. ramp) is the Ram-Lak kernel on the s-grid applied as a linear
     (zero-padded) convolution: h_0 = 1/(4 ds^2), h_n = -1/(pi^2 n^2 ds^2) for odd
     n, 0 for even n != 0; (W g)_k = ds * sum_n h_n g_{k-n}.  R# integrates over
-    theta in [0, pi), so FBP is R# W with no extra factor.
+    theta in [0, pi), so FBP is R# W with no extra factor.  The cosine and Shepp-Logan
+    filters (eqs. cosfilt, SLfilt) multiply the ramp's DFT on the zero-padded s-axis by a
+    window (filter_window), then cut the rows back to n_s samples.
 
 Pins: tests/test_oracle_radon.py (closed forms, brute-force line integrals,
 adjoint identity, direct vs FFT convolution, rotation covariance).
@@ -247,6 +249,65 @@ def ramp_filter(geom, g):
     return out
 
 
-def fbp(geom, g, mode="fft"):
-    """Filtered back-projection R# W g (eq. FBP)."""
-    return radon_adj(geom, ramp_filter(geom, g), mode=mode)
+FILTERS = ("ramlak", "cosine", "shepp-logan")
+
+
+def filter_length(geom):
+    """Length of the zero-padded s-axis on which the filters act: the smallest power of two
+    >= 2 n_s (and >= 16), so that the ramp's circular convolution is the linear one."""
+    lr = 16
+    while lr < 2 * geom.n_s:
+        lr *= 2
+    return lr
+
+
+def filter_window(lr, k, name):
+    """Window of the ramp at centred DFT bin k (|k| <= lr/2) of the padded s-axis (sec. 6,
+    eqs. cosfilt and SLfilt, reading in DESIGN): with sigma_k = |k| / (lr ds) and the
+    s-sampling's Nyquist frequency sigma_N = 1 / (2 ds) = n_s / 4 (the paper's sigma / N with
+    N = n_s and the unit-disc reading of the grids),
+      ramlak       1
+      cosine       cos(2 pi sigma / n_s)   = cos(pi |k| / lr), zero at the Nyquist bin
+      shepp-logan  sinc(sigma / n_s)       = sinc(|k| / (2 lr)), sinc(x) = sin(pi x)/(pi x)."""
+    k = np.abs(np.asarray(k, dtype=np.float64))
+    if name == "ramlak":
+        return np.ones_like(k)
+    if name == "cosine":
+        return np.cos(math.pi * k / lr)
+    if name == "shepp-logan":
+        return np.sinc(k / (2.0 * lr))
+    raise ValueError(f"unknown filter {name!r}")
+
+
+def filter_circulant(geom, x, name):
+    """The filter on one zero-padded row x (length lr) as a circular convolution: the DFT of
+    x times the DFT of the ds-weighted Ram-Lak kernel (placed circularly) times the window."""
+    lr = filter_length(geom)
+    x = np.asarray(x, dtype=np.float64)
+    assert x.shape[-1] == lr
+    ds, ns = geom.ds, geom.n_s
+    h = np.zeros(lr)
+    h[0] = 1.0 / (4.0 * ds * ds)
+    for n in range(1, ns, 2):
+        v = -1.0 / (math.pi ** 2 * n * n * ds * ds)
+        h[n] = v
+        h[lr - n] = v
+    kc = np.fft.fftfreq(lr) * lr                                  # centred bin indices
+    mult = np.fft.fft(h).real * ds * filter_window(lr, kc, name)  # h is even: real DFT
+    return np.fft.ifft(np.fft.fft(x, axis=-1) * mult, axis=-1).real
+
+
+def fbp_filter(geom, g, name="ramlak"):
+    """W_F g for F in FILTERS: each row zero-padded to filter_length, filtered by
+    filter_circulant, cut back to n_s samples.  For "ramlak" this is ramp_filter."""
+    g = np.asarray(g, dtype=np.float64)
+    lr = filter_length(geom)
+    x = np.zeros(g.shape[:-1] + (lr,))
+    x[..., :geom.n_s] = g
+    return filter_circulant(geom, x, name)[..., :geom.n_s]
+
+
+def fbp(geom, g, mode="fft", name="ramlak"):
+    """Filtered back-projection R# W g (eq. FBP) with the filter W of FILTERS."""
+    w = ramp_filter(geom, g) if name == "ramlak" else fbp_filter(geom, g, name)
+    return radon_adj(geom, w, mode=mode)

@@ -158,6 +158,90 @@ def test_ramp_filter_of_gaussian_matches_closed_form():
     assert max(errs) < 1e-12, errs
 
 
+@pytest.mark.parametrize("name", ["cosine", "shepp-logan"])
+def test_windowed_filters_of_gaussian_match_closed_form(name):
+    # The windows act on the ramp's spectrum: cos(2 pi sigma / n_s) is the transform of
+    # (delta(s - 1/n_s) + delta(s + 1/n_s)) / 2 and sinc(sigma / n_s) that of n_s times the
+    # box of width 1/n_s, so for a Gaussian well inside the band W_cos g is the mean of the
+    # ramp's closed form at s -+ 1/n_s and W_SL g its box mean; the latter integrates in
+    # closed form since F' = 1 - 2 u F (F = Dawson): the antiderivative of the ramp's
+    # closed form in s is F(s/s0) / pi^1.5.
+    s0 = 0.1
+    errs = []
+    for n in (128, 256, 512):
+        g = make_geometry(n, 16, n)
+        s = g.s_nodes()
+        G = np.tile(np.exp(-s ** 2 / s0 ** 2), (g.n_theta, 1))
+        W = radon.fbp_filter(g, G, name)
+        a = 1.0 / g.n_s
+        if name == "cosine":
+            ramp = lambda t: (1.0 - 2.0 * (t / s0) * dawsn(t / s0)) / (math.pi ** 1.5 * s0)
+            ref = 0.5 * (ramp(s - a) + ramp(s + a))
+        else:
+            ref = (dawsn((s + a / 2) / s0) - dawsn((s - a / 2) / s0)) / (math.pi ** 1.5 * a)
+        errs.append(rel(W[5], ref))
+        # and not the plain ramp: the windows change the result well above that error
+        assert rel(radon.ramp_filter(g, G)[5], ref) > 1e3 * errs[-1]
+    assert max(errs) < 1e-11, errs
+
+
+def test_windowed_filters_nyquist_and_symmetry():
+    g = make_geometry(32, 8, 24)
+    lr = radon.filter_length(g)
+    assert lr == 64
+    alt = (-1.0) ** np.arange(lr)
+    ramp = radon.filter_circulant(g, alt, "ramlak")
+    # the cosine filter vanishes at the s-sampling's Nyquist frequency (sec. 6) ...
+    assert np.abs(radon.filter_circulant(g, alt, "cosine")).max() < 1e-12 * np.abs(ramp).max()
+    # ... Shepp-Logan keeps sinc(1/4) = 2 sqrt(2) / pi of it
+    sl = radon.filter_circulant(g, alt, "shepp-logan")
+    assert np.allclose(sl, ramp * 2.0 * math.sqrt(2.0) / math.pi, rtol=1e-12, atol=0)
+    # the ramp's Nyquist response is ds sum_n h_n (-1)^n of the Ram-Lak kernel
+    ds = g.ds
+    hsum = 1.0 / (4 * ds * ds) + 2 * sum(1.0 / (math.pi ** 2 * n * n * ds * ds) for n in range(1, g.n_s, 2))
+    assert np.allclose(ramp, alt * ds * hsum, rtol=1e-12, atol=0)
+    # even windows: filtering commutes with reversing s
+    x = inputs.normal_array((g.n_theta, g.n_s), seed=4)
+    for name in radon.FILTERS:
+        w = radon.fbp_filter(g, x, name)
+        wr = radon.fbp_filter(g, x[:, ::-1], name)
+        assert np.allclose(wr, w[:, ::-1], rtol=0, atol=1e-12 * np.abs(w).max()), name
+
+
+def test_windowed_filter_brute_force_dft():
+    # explicit DFT sums on a tiny row, no FFT library
+    g = make_geometry(8, 4, 8)
+    lr = radon.filter_length(g)
+    x = inputs.normal_array((1, g.n_s), seed=9)[0]
+    ds, ns = g.ds, g.n_s
+    h = [0.0] * lr
+    h[0] = ds / (4 * ds * ds)
+    for n in range(1, ns, 2):
+        h[n] = h[lr - n] = -ds / (math.pi ** 2 * n * n * ds * ds)
+    xp = list(x) + [0.0] * (lr - ns)
+    for name in radon.FILTERS:
+        out = []
+        for j in range(ns):
+            acc = 0.0
+            for k in range(lr):
+                kc = k if k <= lr // 2 else k - lr
+                if name == "ramlak":
+                    win = 1.0
+                elif name == "cosine":
+                    win = math.cos(math.pi * abs(kc) / lr)
+                else:
+                    t = math.pi * abs(kc) / (2 * lr)
+                    win = 1.0 if kc == 0 else math.sin(t) / t
+                hk = sum(h[n] * math.cos(2 * math.pi * k * n / lr) for n in range(lr))
+                xk = complex(sum(xp[n] * math.cos(2 * math.pi * k * n / lr) for n in range(lr)),
+                             -sum(xp[n] * math.sin(2 * math.pi * k * n / lr) for n in range(lr)))
+                e = complex(math.cos(2 * math.pi * k * j / lr), math.sin(2 * math.pi * k * j / lr))
+                acc += (xk * hk * win * e).real
+            out.append(acc / lr)
+        got = radon.fbp_filter(g, x[None, :], name)[0]
+        assert np.allclose(got, out, rtol=0, atol=1e-12 * max(abs(v) for v in out)), name
+
+
 def test_fbp_recovers_smooth_object():
     # FBP = R# W R.  Like R#, its accuracy is set by the fine-lattice oversampling: ~1e-2 at
     # the sampling bounds, ~1e-4 with r and N_rho both about twice their bounds.
