@@ -54,9 +54,13 @@ typedef enum {
 /* Operation selector for rl_workspace_bytes. */
 typedef enum { RL_OP_FWD = 0, RL_OP_ADJ = 1, RL_OP_FBP = 2 } rl_op;
 
-/* Filters of filtered back-projection (sec. 6, eq. ramp).  Only the ramp (Ram-Lak)
- * filter is implemented; other values return RL_ERR_INVALID_ARG. */
-typedef enum { RL_FILTER_RAMLAK = 0 } rl_filter;
+/* Filters of filtered back-projection (sec. 6, eqs. ramp, cosfilt, SLfilt).  The ramp
+ * is the Ram-Lak kernel; cosine and Shepp-Logan multiply the ramp's spectrum on the
+ * zero-padded s-axis (length lr, the smallest power of two >= 2 n_s and >= 16) at bin k,
+ * |k| <= lr / 2, by cos(pi |k| / lr) and sinc(|k| / (2 lr)) (sinc(x) = sin(pi x) / (pi x)):
+ * the paper's cos(2 pi sigma / N) and sinc(sigma / N) with sigma = |k| / (lr ds), N = n_s.
+ * Other values return RL_ERR_INVALID_ARG. */
+typedef enum { RL_FILTER_RAMLAK = 0, RL_FILTER_COSINE = 1, RL_FILTER_SHEPP_LOGAN = 2 } rl_filter;
 
 /*
  * Geometry: every field fixes the discrete operator (changing any of them changes
@@ -139,10 +143,13 @@ rl_status radon_adj(const rl_plan* plan, const float* d_sino, float* d_img, int3
 rl_status radon_transpose(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch,
                           void* d_ws, size_t ws_bytes, hipStream_t stream);
 
-/* Filtered back-projection f = R# W g (sec. 1 eq. FBP): W is the ramp filter |sigma| of
- * sec. 6 eq. (ramp), applied along s as a linear (zero-padded) convolution with the
- * Ram-Lak kernel h_0 = 1/(4 ds^2), h_n = -1/(pi^2 n^2 ds^2) for odd n, 0 for even n != 0
- * (times ds), then radon_adj.  d_sino [batch][n_theta][n_s] -> d_img [batch][n][n]. */
+/* Filtered back-projection f = R# W g (sec. 1 eq. FBP): W is the filter of sec. 6 chosen by
+ * `filter`, applied along s: the ramp |sigma| (eq. ramp) as a linear (zero-padded)
+ * convolution with the Ram-Lak kernel h_0 = 1/(4 ds^2), h_n = -1/(pi^2 n^2 ds^2) for odd n,
+ * 0 for even n != 0 (times ds); cosine and Shepp-Logan as that ramp's spectrum times their
+ * window (see rl_filter) on the zero-padded axis, cut back to n_s samples; then radon_adj.
+ * d_sino [batch][n_theta][n_s] -> d_img [batch][n][n].  A filter value outside rl_filter
+ * returns RL_ERR_INVALID_ARG before any launch. */
 rl_status fbp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch,
               rl_filter filter, void* d_ws, size_t ws_bytes, hipStream_t stream);
 

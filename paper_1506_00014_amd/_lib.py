@@ -24,6 +24,9 @@ STATUS_NAMES = {
 }
 RL_OP_FWD, RL_OP_ADJ, RL_OP_FBP = 0, 1, 2
 RL_FILTER_RAMLAK = 0
+RL_FILTER_COSINE = 1
+RL_FILTER_SHEPP_LOGAN = 2
+FILTERS = {"ramlak": RL_FILTER_RAMLAK, "cosine": RL_FILTER_COSINE, "shepp-logan": RL_FILTER_SHEPP_LOGAN}
 RL_STAGE_PREFILTER, RL_STAGE_LOGPOLAR, RL_STAGE_CONV, RL_STAGE_KERNEL = 0, 1, 2, 3
 
 # Every function declared in include/radonlp.h.

@@ -114,11 +114,13 @@ class RadonPlan:
         sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
         return self._run("radon_transpose", sino, (g["n"], g["n"]), _lib.RL_OP_ADJ, ws)
 
-    def fbp(self, sino, ws=None):
-        """R# W g with the Ram-Lak filter: [..., n_theta, n_s] -> [..., n, n]."""
+    def fbp(self, sino, ws=None, filter="ramlak"):
+        """R# W g, W the "ramlak", "cosine" or "shepp-logan" filter: [..., n_theta, n_s] -> [..., n, n]."""
+        if filter not in _lib.FILTERS:
+            raise ValueError(f"unknown filter {filter!r}; one of {sorted(_lib.FILTERS)}")
         g = self.geom
         sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
-        return self._run("fbp", sino, (g["n"], g["n"]), _lib.RL_OP_FBP, ws, extra=(_lib.RL_FILTER_RAMLAK,))
+        return self._run("fbp", sino, (g["n"], g["n"]), _lib.RL_OP_FBP, ws, extra=(_lib.FILTERS[filter],))
 
     def debug_stage(self, stage, img):
         """Intermediate of the forward chain for one slice (see rl_debug_stage)."""
@@ -166,8 +168,8 @@ def radon_transpose(plan: RadonPlan, sino, ws=None):
     return plan.transpose(sino, ws)
 
 
-def fbp(plan: RadonPlan, sino, ws=None):
-    return plan.fbp(sino, ws)
+def fbp(plan: RadonPlan, sino, ws=None, filter="ramlak"):
+    return plan.fbp(sino, ws, filter=filter)
 
 
 class RadonFn(torch.autograd.Function):

@@ -671,11 +671,13 @@ rl_status launch_lp2cart_adj(const rl_plan* p, const float* U, float* cbar, int 
   return check_launch("k_lp2cart_adj");
 }
 
-// ------------------------------------------------------------------ ramp filter
-// One sinogram row per block: zero-pad to lr, real FFT, multiply by the real ramp
-// multiplier, inverse real FFT, keep the first n_s samples.  The multiplier is applied
-// pairwise (k, lr/2 - k) in place between the two packings.
-__global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __restrict__ in, float* __restrict__ out) {
+// ------------------------------------------------------------------ FBP filter
+// One sinogram row per block: zero-pad to lr, real FFT, multiply by the real multiplier of
+// the filter (the Ram-Lak ramp, times the cosine or Shepp-Logan window), inverse real FFT,
+// keep the first n_s samples.  The multiplier is applied pairwise (k, lr/2 - k) in place
+// between the two packings.
+__global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __restrict__ in, float* __restrict__ out,
+                                                   int filter) {
   extern __shared__ float2 sh[];
   const int ncr = P.lr / 2, ns = P.n_s;
   const size_t row = blockIdx.x;
@@ -685,6 +687,7 @@ __global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __res
   __syncthreads();
   fft_lds<kRowVals, false>(sh, ncr, 1, P.twp_ramp);
   const int step = P.tw_len / P.lr;
+  const float* mult = P.ramp + (size_t)filter * (ncr + 1);
   for (int k = threadIdx.x; k <= ncr / 2; k += blockDim.x) {
     const int km = ncr - k;
     const float2 a = sh[k];
@@ -699,8 +702,8 @@ __global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __res
     };
     float2 Xk = post(a, bz, k);
     float2 Xm = post(bz, a, km);
-    Xk = cscale(Xk, P.ramp[k]);
-    Xm = cscale(Xm, P.ramp[km]);
+    Xk = cscale(Xk, mult[k]);
+    Xm = cscale(Xm, mult[km]);
     // inverse packing from (Y[k], Y[km])
     auto pre = [&](float2 ya, float2 yb, int kk) {
       const float2 bb = cconj(yb);
@@ -725,10 +728,10 @@ __global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __res
   for (int i = threadIdx.x; i < ns; i += blockDim.x) dst[i] = xs[i];
 }
 
-rl_status launch_ramp(const rl_plan* p, const float* in, float* out, int batch, hipStream_t s) {
+rl_status launch_ramp(const rl_plan* p, const float* in, float* out, int batch, int filter, hipStream_t s) {
   const DevPlan& d = p->d;
   RL_LAUNCH("k_ramp", k_ramp, dim3(batch * d.n_theta), dim3(kThreads), (size_t)(d.lr / 2) * sizeof(float2), s, d, in,
-                     out);
+            out, filter);
   return check_launch("k_ramp");
 }
 
@@ -798,11 +801,12 @@ extern "C" rl_status radon_transpose(const rl_plan* plan, const float* d_sino, f
 
 extern "C" rl_status fbp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, rl_filter filter,
                          void* d_ws, size_t ws_bytes, hipStream_t stream) {
-  if (filter != RL_FILTER_RAMLAK) return fail(RL_ERR_INVALID_ARG, "only RL_FILTER_RAMLAK is implemented");
+  if (filter != RL_FILTER_RAMLAK && filter != RL_FILTER_COSINE && filter != RL_FILTER_SHEPP_LOGAN)
+    return fail(RL_ERR_INVALID_ARG, "unknown filter");
   rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_FBP);
   if (st != RL_OK || batch == 0) return st;
   const WsLayout L = workspace_layout(plan, batch, RL_OP_FBP);
   float* wg = (float*)((char*)d_ws + L.off[4]);
-  if ((st = launch_ramp(plan, d_sino, wg, batch, stream)) != RL_OK) return st;
+  if ((st = launch_ramp(plan, d_sino, wg, batch, (int)filter, stream)) != RL_OK) return st;
   return adjoint_chain(plan, wg, d_img, batch, d_ws, RL_OP_FBP, false, stream);
 }

@@ -460,8 +460,9 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
     for (int n2 = 0; n2 < K2; ++n2)
       for (int k1 = 0; k1 < K1; ++k1) tw_theta[(size_t)n2 * K1 + k1] = tw[(size_t)n2 * k1 * step];
   }
-  // Ram-Lak kernel (times ds) on a cyclic grid of length lr, and its DFT / lr (real, even)
-  std::vector<float> ramp(d.lr / 2 + 1);
+  // Ram-Lak kernel (times ds) on a cyclic grid of length lr, and its DFT / lr (real, even),
+  // times the window of each filter of rl_filter: table f at ramp[f * (lr / 2 + 1) + k]
+  std::vector<float> ramp(3 * (d.lr / 2 + 1));
   {
     const int lr = d.lr;
     std::vector<double> h(lr, 0.0);
@@ -477,7 +478,10 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
     for (int k = 0; k <= lr / 2; ++k) {
       double acc = h[0];
       for (int n = 1; n < g.n_s; n += 2) acc += 2.0 * h[n] * std::cos(2.0 * M_PI * (double)((long)k * n % lr) / lr);
-      ramp[k] = (float)(acc / lr);
+      const double r0 = acc / lr, t = M_PI * k / (2.0 * lr);
+      ramp[k] = (float)r0;
+      ramp[(lr / 2 + 1) + k] = (float)(r0 * std::cos(M_PI * k / lr));
+      ramp[2 * (lr / 2 + 1) + k] = (float)(k == 0 ? r0 : r0 * std::sin(t) / t);
     }
   }
   std::vector<double> erho(g.n_rho);

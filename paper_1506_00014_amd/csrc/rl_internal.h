@@ -38,7 +38,7 @@ struct DevPlan {
   const float2* twp_ramp;  // Stockham pass twiddles of length lr / 2 (ramp filter rows)
   const float2* tw_theta;  // [k_theta] four-step twiddles exp(-2 pi i n2 k1 / k_theta) at
                            // n2 * K1 + k1 (K1 x K2 = k_theta as the theta pass splits it)
-  const float* ramp;       // [lr/2 + 1] ramp multiplier (real), includes 1/lr
+  const float* ramp;       // [3][lr/2 + 1] filter multipliers (rl_filter order), include 1/lr
   const float* pref;       // [kPrefR + 1] prefilter taps sqrt(3) z^|k|
   const double* erho;      // [n_rho] e^{rho_q} / (a_R dx): image-index length of the ray at rho_q
   const int2* tau;         // [m][n_own][n_s] rho position tau of S_m(theta_j, s_k) on each owned
@@ -112,7 +112,7 @@ rl_status launch_irfft_scale(const rl_plan* p, const float2* spec, float* u, int
                              hipStream_t s);
 rl_status launch_lp2cart_adj(const rl_plan* p, const float* u, float* cbar, int batch,
                              hipStream_t s);
-rl_status launch_ramp(const rl_plan* p, const float* in, float* out, int batch, hipStream_t s);
+rl_status launch_ramp(const rl_plan* p, const float* in, float* out, int batch, int filter, hipStream_t s);
 rl_status launch_irfft_rows(const rl_plan* p, const float2* spec, float* out, int rows,
                             hipStream_t s);
 // The theta pass splits k_theta = K1 K2 (four-step FFT); K1 as a function of k_theta.

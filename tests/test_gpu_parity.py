@@ -137,6 +137,39 @@ def test_fbp_parity(dev, case):
     assert e <= TOL
 
 
+@pytest.mark.parametrize("filt", ["cosine", "shepp-logan"])
+@pytest.mark.parametrize("case", CASES[:2], ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
+def test_fbp_filter_parity(dev, case, filt):
+    n, nt, ns, m, kw = case
+    plan, og = get_plan(n, nt, ns, m, **kw)
+    img, ells = inputs.ellipse_phantom(n, 8, 102)
+    from oracle import analytic
+
+    g = analytic.ellipse_sino(og.theta_nodes(), og.s_nodes(), ells)
+    got = plan.fbp(to_dev(g, dev), filter=filt).cpu().numpy()
+    ref = oradon.fbp(og, f32(g), name=filt)
+    e = rel(got, ref)
+    print(f"FBP {filt} {case}: rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
+    # the window changes the result well above the tolerance
+    assert rel(plan.fbp(to_dev(g, dev)).cpu().numpy(), ref) > 10 * TOL
+
+
+def test_fbp_unknown_filter(dev):
+    plan, og = get_plan(*CASES[1][:4], **CASES[1][4])
+    g = torch.zeros(og.n_theta, og.n_s, device=dev)
+    with pytest.raises(ValueError):
+        plan.fbp(g, filter="hann")
+    from paper_1506_00014_amd import _lib
+    import ctypes
+    lib = _lib.load()
+    ws = torch.empty(plan.workspace_bytes(1, _lib.RL_OP_FBP), dtype=torch.uint8, device=dev)
+    out = torch.empty(og.n, og.n, device=dev)
+    st = lib.fbp(plan._ptr, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr()), 1, 3,
+                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
+    assert st == _lib.RL_ERR_INVALID_ARG
+
+
 def test_stage_parity(dev):
     from paper_1506_00014_amd import _lib
 
