@@ -349,12 +349,14 @@ def main():
         "R": (lambda: plan.forward(f, ws), lambda i: plan.forward(f[i], ws1)),
         "R#": (lambda: plan.adjoint(sino, ws), lambda i: plan.adjoint(sino[i], ws1)),
         "FBP": (lambda: plan.fbp(sino, ws), lambda i: plan.fbp(sino[i], ws1)),
+        "FBP cosine": (lambda: plan.fbp(sino, ws, filter="cosine"), None),
+        "FBP shepp-logan": (lambda: plan.fbp(sino, ws, filter="shepp-logan"), None),
     }
     detail = {"per_op": {}, "kernels": kernels}
     for op, (batched, single) in ops.items():
         tb = time_op(batched, reps)
         rec = {"batched_slices_per_s": round(B / (tb / 1000.0), 1), "batched_ms_per_slice": round(tb / B, 4)}
-        if not args.no_plain:
+        if single is not None and not args.no_plain:
             tp = time_op(lambda: [single(i) for i in range(B)], 1)
             rec["plain_slices_per_s"] = round(B / (tp / 1000.0), 1)
             rec["batched_over_plain"] = round(tp / tb, 3)
