@@ -18,6 +18,7 @@ Modules
             multiplier H = zeta_hat / (B_hat_rho * D_hat_theta)
   radon     Algorithm 1 (fast Radon transform) step by step, its exact
             weighted transpose (the back-projection), and FBP (eq. FBP, ramp)
+  em        EM reconstruction step (sec. 7) on radon_fwd / radon_adj
   analytic  closed-form Radon transforms (disc, Gaussian, ellipse) used as pins
   brute     brute-force line integrals of the spline interpolant (pin)
   closed_form  the paper's closed form for P(mu, alpha, beta) (eq.
