@@ -51,8 +51,8 @@ typedef enum {
   RL_ERR_INTERNAL = 6
 } rl_status;
 
-/* Operation selector for rl_workspace_bytes. */
-typedef enum { RL_OP_FWD = 0, RL_OP_ADJ = 1, RL_OP_FBP = 2 } rl_op;
+/* Operation selector for rl_workspace_bytes (RL_OP_EM: rl_em and, with batch 1, rl_em_norm). */
+typedef enum { RL_OP_FWD = 0, RL_OP_ADJ = 1, RL_OP_FBP = 2, RL_OP_EM = 3 } rl_op;
 
 /* Filters of filtered back-projection (sec. 6, eqs. ramp, cosfilt, SLfilt).  The ramp
  * is the Ram-Lak kernel; cosine and Shepp-Logan multiply the ramp's spectrum on the
@@ -152,6 +152,26 @@ rl_status radon_transpose(const rl_plan* plan, const float* d_sino, float* d_img
  * returns RL_ERR_INVALID_ARG before any launch. */
 rl_status fbp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch,
               rl_filter filter, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* EM reconstruction (sec. 7, the EM iteration), on radon_fwd and radon_adj:
+ *   f <- f R#( chi_C g / R f ) / R# chi_C,
+ * chi_C(theta, s) = 1 on the lines through the unit disc (|s| < 1) and 0 elsewhere.  Where
+ * the paper is silent: the ratio is 0 on lines with R f <= 0, and the image lives on the
+ * unit disc (the support of f, the only part R reads): f is set to 0 at pixels with
+ * |x| >= 1 (node coordinates x = -1 + i dx) or where R# chi_C <= 0.
+ *
+ * rl_em_norm writes the normalisation image R# chi_C, d_norm [n][n] (computed once per
+ * plan).  Workspace: rl_workspace_bytes(plan, 1, RL_OP_EM).
+ *
+ * rl_em runs `iters` EM steps in place on d_img [batch][n][n] (the start image, > 0 on the
+ * disc) for the data d_sino [batch][n_theta][n_s] (>= 0) and the normalisation d_norm from
+ * rl_em_norm.  Workspace: rl_workspace_bytes(plan, batch, RL_OP_EM); it holds R f and the
+ * back-projected ratio between the steps.  batch == 0 or iters == 0 is a no-op; negative
+ * values return RL_ERR_INVALID_ARG, as do NULL pointers and an image that overlaps the
+ * data, the normalisation or the workspace. */
+rl_status rl_em_norm(const rl_plan* plan, float* d_norm, void* d_ws, size_t ws_bytes, hipStream_t stream);
+rl_status rl_em(const rl_plan* plan, const float* d_sino, const float* d_norm, float* d_img, int32_t batch,
+                int32_t iters, void* d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* rl_last_error(void);

@@ -22,7 +22,7 @@ STATUS_NAMES = {
     5: "RL_ERR_UNSUPPORTED_ARCH",
     6: "RL_ERR_INTERNAL",
 }
-RL_OP_FWD, RL_OP_ADJ, RL_OP_FBP = 0, 1, 2
+RL_OP_FWD, RL_OP_ADJ, RL_OP_FBP, RL_OP_EM = 0, 1, 2, 3
 RL_FILTER_RAMLAK = 0
 RL_FILTER_COSINE = 1
 RL_FILTER_SHEPP_LOGAN = 2
@@ -52,6 +52,8 @@ EXPORTED = (
     "rl_batch_fwd",
     "rl_batch_adj",
     "rl_batch_destroy",
+    "rl_em_norm",
+    "rl_em",
 )
 
 
@@ -134,6 +136,10 @@ def load(path: str = LIB_PATH):
         f.restype = c_int32
     lib.rl_batch_destroy.argtypes = [c_void_p]
     lib.rl_batch_destroy.restype = None
+    lib.rl_em_norm.argtypes = [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.rl_em_norm.restype = c_int32
+    lib.rl_em.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_size_t, c_void_p]
+    lib.rl_em.restype = c_int32
     _lib = lib
     return lib
 

@@ -122,6 +122,44 @@ class RadonPlan:
         sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
         return self._run("fbp", sino, (g["n"], g["n"]), _lib.RL_OP_FBP, ws, extra=(_lib.FILTERS[filter],))
 
+    def em_norm(self, ws=None):
+        """R# chi_C, the normalisation of the EM step: [n, n] (rl_em_norm)."""
+        g = self.geom
+        out = torch.empty(g["n"], g["n"], dtype=torch.float32, device=self.device)
+        need = self.workspace_bytes(1, _lib.RL_OP_EM)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            st = self._lib.rl_em_norm(self._ptr, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                      ctypes.c_size_t(ws.numel()), _stream_ptr(self.device))
+        _lib.check("rl_em_norm", st)
+        return out
+
+    def em(self, sino, img, iters, norm=None, ws=None):
+        """`iters` EM steps (rl_em) from the start image `img` for the data `sino`:
+        [..., n_theta, n_s], [..., n, n] -> a new [..., n, n] tensor."""
+        g = self.geom
+        sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
+        f = self._check_in(img, (g["n"], g["n"]), "img").clone()
+        if sino.shape[:-2] != f.shape[:-2]:
+            raise ValueError("sino and img must have the same leading shape")
+        if norm is None:
+            norm = self.em_norm()
+        norm = self._check_in(norm, (g["n"], g["n"]), "norm")
+        lead = f.shape[:-2]
+        batch = int(math.prod(lead)) if lead else 1
+        if batch == 0 or iters == 0:
+            return f
+        need = self.workspace_bytes(batch, _lib.RL_OP_EM)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            st = self._lib.rl_em(self._ptr, ctypes.c_void_p(sino.data_ptr()), ctypes.c_void_p(norm.data_ptr()),
+                                 ctypes.c_void_p(f.data_ptr()), batch, int(iters), ctypes.c_void_p(ws.data_ptr()),
+                                 ctypes.c_size_t(ws.numel()), _stream_ptr(self.device))
+        _lib.check("rl_em", st)
+        return f
+
     def debug_stage(self, stage, img):
         """Intermediate of the forward chain for one slice (see rl_debug_stage)."""
         g = self.geom

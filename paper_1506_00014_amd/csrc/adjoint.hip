@@ -765,6 +765,10 @@ rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int b
   return check_plan_device(plan);
 }
 
+}  // namespace
+
+namespace rl {
+
 rl_status adjoint_chain(const rl_plan* plan, const float* sino, float* img, int batch, void* ws, rl_op op,
                         bool transpose, hipStream_t s) {
   const DevPlan& d = plan->d;
@@ -783,7 +787,7 @@ rl_status adjoint_chain(const rl_plan* plan, const float* sino, float* img, int 
   return launch_prefilter(plan, cbar, img, batch, (float)scale, s);
 }
 
-}  // namespace
+}  // namespace rl
 
 extern "C" rl_status radon_adj(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, void* d_ws,
                                size_t ws_bytes, hipStream_t stream) {

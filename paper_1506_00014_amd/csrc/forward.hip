@@ -683,6 +683,10 @@ rl_status common_checks(const rl_plan* plan, const void* in, const void* out, in
   return check_plan_device(plan);
 }
 
+}  // namespace
+
+namespace rl {
+
 rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int batch, void* ws, int stop_stage,
                         float* stage_out, hipStream_t s) {
   const DevPlan& d = plan->d;
@@ -704,7 +708,7 @@ rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int 
   return launch_irfft_eval(plan, Bs, sino, batch, s);
 }
 
-}  // namespace
+}  // namespace rl
 
 extern "C" rl_status radon_fwd(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch, void* d_ws,
                                size_t ws_bytes, hipStream_t stream) {

@@ -669,6 +669,7 @@ extern "C" rl_status rl_plan_geometry(const rl_plan* plan, rl_geom* out) {
 
 extern "C" size_t rl_workspace_bytes(const rl_plan* plan, int32_t batch, rl_op op) {
   if (!plan || batch <= 0) return 0;
+  if (op == RL_OP_EM) return em_workspace_bytes(plan, batch);
   if (op != RL_OP_FWD && op != RL_OP_ADJ && op != RL_OP_FBP) return 0;
   return workspace_layout(plan, batch, op).total;
 }

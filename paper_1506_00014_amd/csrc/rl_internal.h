@@ -120,6 +120,14 @@ constexpr int theta_k1(int k_theta) { return k_theta <= 32 ? k_theta : 32; }
 // Plan time (host): image boxes of the forward blocks, in the order of the forward grid.
 std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& cs,
                                   const std::vector<int2>& fq, const std::vector<double>& erho);
+// The operator chains behind radon_fwd and radon_adj / radon_transpose / fbp (arguments
+// checked by the caller; ws holds workspace_layout(plan, batch, RL_OP_FWD or op)).
+rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int batch, void* ws, int stop_stage,
+                        float* stage_out, hipStream_t s);
+rl_status adjoint_chain(const rl_plan* plan, const float* sino, float* img, int batch, void* ws, rl_op op,
+                        bool transpose, hipStream_t s);
+// Workspace of rl_em / rl_em_norm (em.hip).
+size_t em_workspace_bytes(const rl_plan* plan, int batch);
 // Plan time: build the adjoint splat passes (allocates plan->d_adj, fills the adj_* fields).
 rl_status build_adj_passes(rl_plan* p);
 // Plan time: raise the LDS limits of the kernels this plan launches (see ensure_dyn_lds).
