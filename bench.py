@@ -173,6 +173,21 @@ def cpu_baseline(g, seed=303, parts=3):
     }
 
 
+def em_detail(plan, f, sino, B, reps, time_op, detail, log):
+    """One EM step (R, ratio, R#, update) on the whole batch; the normalisation R# chi_C is
+    computed once, outside the timed region."""
+    import torch
+    from paper_1506_00014_amd import _lib
+
+    em_norm = plan.em_norm()
+    f_em = torch.ones_like(f)
+    em_ws = torch.empty(plan.workspace_bytes(B, _lib.RL_OP_EM), dtype=torch.uint8, device=f.device)
+    t_em = time_op(lambda: plan.em(sino, f_em, 1, norm=em_norm, ws=em_ws), reps)
+    detail["per_op"]["EM step"] = {"batched_slices_per_s": round(B / (t_em / 1000.0), 1),
+                                   "batched_ms_per_slice": round(t_em / B, 4)}
+    log(f"EM step: {detail['per_op']['EM step']}")
+
+
 def ragged_detail(torch, log, count=256, seed=401):
     """Ragged batch: `count` slices with N drawn from {256, 512, 768, 1024} (N x N sinograms),
     R and R# for the whole set as one replay of a captured graph vs one plain call per slice."""
@@ -237,6 +252,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch detail measurement")
+    ap.add_argument("--no-em", action="store_true",
+                    help="skip the EM step measurement (its normalisation is a batch-1 back-projection)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (FETCH_SIZE / WRITE_SIZE calibration)")
     args = ap.parse_args()
@@ -363,13 +380,8 @@ def main():
         detail["per_op"][op] = rec
         log(f"{op}: {rec}")
     # EM reconstruction: one step (R, ratio, R#, update) on the whole batch
-    em_norm = plan.em_norm()
-    f_em = torch.ones_like(f)
-    em_ws = torch.empty(plan.workspace_bytes(B, _lib.RL_OP_EM), dtype=torch.uint8, device=f.device)
-    t_em = time_op(lambda: plan.em(sino, f_em, 1, norm=em_norm, ws=em_ws), reps)
-    detail["per_op"]["EM step"] = {"batched_slices_per_s": round(B / (t_em / 1000.0), 1),
-                                   "batched_ms_per_slice": round(t_em / B, 4)}
-    log(f"EM step: {detail['per_op']['EM step']}")
+    if not args.no_em:
+        em_detail(plan, f, sino, B, reps, time_op, detail, log)
     if not args.no_ragged:
         detail["ragged_batch"] = ragged_detail(torch, log)
     detail["paper_context"] = ("GTX 770, CUDA 7, FP32, M=3, N_theta=1.5N: EM 100 steps on 2048 slices of 2048^2 "
