@@ -136,7 +136,8 @@ rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int ba
 // ------------------------------------------------------------------ cart -> log-polar
 constexpr int kFQ = 64;         // rho indices per block: one per lane of a wave
 constexpr int kFRows = 8;       // coarse rows per block
-constexpr int kFPatch = 8448;   // floats of the LDS image patch
+constexpr int kFPatch = 8448;   // floats of the LDS image patch (large tiles)
+constexpr int kFPatchSmall = 5504;  // patch of the small tiles: four blocks per CU fit in LDS
 constexpr int kFThreads = 512;  // threads per block
 static_assert(kFQ == 64, "the sample loop maps rho indices to the lanes of a wave");
 
@@ -165,14 +166,19 @@ __device__ __forceinline__ float bicubic_at(double X, double Y, int n, Tap tap) 
 //    samples of one fine ray at a time, a lane per rho index, into an LDS buffer; samples
 //    outside D are zero.  3) Each coarse sample is the decimation filter over the fine rows
 //    around it, times e^rho.
-__global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const float* __restrict__ c, float* __restrict__ u) {
+template <int PATCH>
+__global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __restrict__ tiles,
+                                                        const float* __restrict__ c, float* __restrict__ u) {
   extern __shared__ float smem[];
   float* patch = smem;
-  float* vbuf = smem + kFPatch;
-  const int q0 = blockIdx.x * kFQ;
-  const int bm = blockIdx.z;
-  const int b = bm / P.m, m = bm - b * P.m;
-  const int i0 = blockIdx.y * kFRows;
+  float* vbuf = smem + PATCH;
+  // tile (m, by, bx) from the plan's list for this patch size; slice from blockIdx.y
+  const int gx = (P.n_rho + kFQ - 1) / kFQ, gy = (P.n_sup + kFRows - 1) / kFRows;
+  const int tile = tiles[blockIdx.x];
+  const int bx = tile % gx, by = (tile / gx) % gy, m = tile / (gx * gy);
+  const int b = blockIdx.y, bm = b * P.m + m;
+  const int q0 = bx * kFQ;
+  const int i0 = by * kFRows;
   const int i1 = min(i0 + kFRows, P.n_sup);
   const int n = P.n, r = P.r;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -191,7 +197,7 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const float* _
   const int tclo = max(tlo, P.t_min), tchi = min(thi, P.t_min + P.n_fine - 1);
   const int qlast = min(q0 + kFQ, P.n_rho) - 1;
   // image box of the block's samples, built with the plan (W == 0: no sample inside D)
-  const int4 box = P.fbox[((size_t)m * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x];
+  const int4 box = P.fbox[tile];
   if (box.z == 0) {
     for (int o = threadIdx.x; o < (i1 - i0) * kFQ; o += blockDim.x) {
       const int il = o / kFQ, ql = o - il * kFQ;
@@ -213,7 +219,7 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const float* _
   if (threadIdx.x < kFQ) se[threadIdx.x] = q0 + (int)threadIdx.x <= qlast ? P.erho[q0 + threadIdx.x] : 0.0;
   const int Xlo = box.x, Ylo = box.y, W = box.z, H = box.w;
   const int Wp = W | 1;  // odd pitch spreads rows over the LDS banks
-  const bool staged = Wp * H <= kFPatch;
+  const bool staged = Wp * H <= PATCH;
   {
     if (staged) {
       // groups of four consecutive pixels in flat order; (ly, lg) advance by the block stride
@@ -387,20 +393,44 @@ std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& 
   return out;
 }
 
-static size_t cart2lp_lds(const DevPlan& d) {
+static size_t cart2lp_lds(const DevPlan& d, int patch) {
   const int nft = d.r * (kFRows + 3) - 1;
-  return (size_t)(kFPatch + nft * kFQ) * sizeof(float) + (size_t)nft * (sizeof(double2) + sizeof(int2)) +
+  return (size_t)(patch + nft * kFQ) * sizeof(float) + (size_t)nft * (sizeof(double2) + sizeof(int2)) +
          kFQ * sizeof(double);
 }
 
+// The plan lists the tiles whose image box fits kFPatchSmall (and those with no sample in D)
+// first, then the others; each list runs with its own LDS size, so that the small tiles,
+// most of them, run four blocks per CU.
+// The timing hooks record the two launches as one k_cart2lp interval.
 rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
-  const size_t lds = cart2lp_lds(d);
-  rl_status st = ensure_dyn_lds((const void*)k_cart2lp, lds, "hipFuncSetAttribute(k_cart2lp)");
-  if (st != RL_OK) return st;
-  dim3 grid((d.n_rho + kFQ - 1) / kFQ, (d.n_sup + kFRows - 1) / kFRows, batch * d.m);
-  RL_LAUNCH("k_cart2lp", k_cart2lp, grid, dim3(kFThreads), lds, s, d, c, u);
-  return check_launch("k_cart2lp");
+  const int slot = prof_open("k_cart2lp", s);
+  rl_status st = RL_OK;
+  if (d.ftiles_small > 0) {
+    hipLaunchKernelGGL(k_cart2lp<kFPatchSmall>, dim3(d.ftiles_small, batch), dim3(kFThreads),
+                       cart2lp_lds(d, kFPatchSmall), s, d, d.ftiles, c, u);
+    st = check_launch("k_cart2lp");
+  }
+  if (st == RL_OK && d.ftiles_large > 0) {
+    hipLaunchKernelGGL(k_cart2lp<kFPatch>, dim3(d.ftiles_large, batch), dim3(kFThreads), cart2lp_lds(d, kFPatch), s,
+                       d, d.ftiles + d.ftiles_small, c, u);
+    st = check_launch("k_cart2lp");
+  }
+  prof_close(slot, s);
+  return st;
+}
+
+// Plan time (host): the tile lists of launch_cart2lp, from the image boxes.
+std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small) {
+  std::vector<int> small, large;
+  for (int t = 0; t < (int)boxes.size(); ++t) {
+    const int4 bx = boxes[t];
+    ((bx.z == 0 || (bx.z | 1) * bx.w <= kFPatchSmall) ? small : large).push_back(t);
+  }
+  *n_small = (int)small.size();
+  small.insert(small.end(), large.begin(), large.end());
+  return small;
 }
 
 // ------------------------------------------------------------------ rho FFTs of rows
@@ -570,7 +600,10 @@ static rl_status theta_prepare() {
 }
 
 rl_status prepare_forward_launches(const rl_plan* p) {
-  rl_status st = ensure_dyn_lds((const void*)k_cart2lp, cart2lp_lds(p->d), "hipFuncSetAttribute(k_cart2lp)");
+  rl_status st = ensure_dyn_lds((const void*)k_cart2lp<kFPatchSmall>, cart2lp_lds(p->d, kFPatchSmall),
+                                "hipFuncSetAttribute(k_cart2lp)");
+  if (st != RL_OK) return st;
+  st = ensure_dyn_lds((const void*)k_cart2lp<kFPatch>, cart2lp_lds(p->d, kFPatch), "hipFuncSetAttribute(k_cart2lp)");
   if (st != RL_OK) return st;
   switch (p->d.k_theta) {
     case 8: return theta_prepare<8, 1>();

@@ -493,6 +493,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   }
 
   const std::vector<int4> fbox = build_fwd_boxes(d, fine_cs, fine_q, erho);
+  int n_small_tiles = 0;
+  const std::vector<int> ftiles = build_fwd_tiles(fbox, &n_small_tiles);
 
   // ---------------- kernel table: zeta_hat on the device in FP64
   const int nkt = g.k_theta / 2 + 1, nkr = g.n_rho / 2 + 1;
@@ -534,6 +536,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   const size_t o_dt = off; off += al(sizeof(float) * dtap.size());
   const size_t o_ta = off; off += al(sizeof(int2) * (size_t)M * n_own * g.n_s);
   const size_t o_fb = off; off += al(sizeof(int4) * fbox.size());
+  const size_t o_ft = off; off += al(sizeof(int) * ftiles.size());
   const size_t table_bytes = off;
   // scratch for the quadrature (freed before returning)
   const size_t s_u = 0, s_a = al(sizeof(double) * n_nodes_pad), s_l = 2 * s_a, s_z = 3 * s_a;
@@ -606,6 +609,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
       {o_er, erho.data(), sizeof(double) * erho.size()},
       {o_dt, dtap.data(), sizeof(float) * dtap.size()},
       {o_fb, fbox.data(), sizeof(int4) * fbox.size()},
+      {o_ft, ftiles.data(), sizeof(int) * ftiles.size()},
   };
   for (auto& up : ups)
     if ((st = check_hip(hipMemcpy(mem + up.off, up.src, up.bytes, hipMemcpyHostToDevice), "upload table")) != RL_OK)
@@ -626,6 +630,9 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   d.dtap = (const float*)(mem + o_dt);
   d.tau = (const int2*)(mem + o_ta);
   d.fbox = (const int4*)(mem + o_fb);
+  d.ftiles = (const int*)(mem + o_ft);
+  d.ftiles_small = n_small_tiles;
+  d.ftiles_large = (int)ftiles.size() - n_small_tiles;
   hipLaunchKernelGGL(k_tau_table, dim3(n_own, M), dim3(256), 0, 0, d, (int2*)(mem + o_ta));
   if ((st = check_launch("k_tau_table")) != RL_OK) return cleanup(st);
   if ((st = check_hip(hipDeviceSynchronize(), "k_tau_table")) != RL_OK) return cleanup(st);

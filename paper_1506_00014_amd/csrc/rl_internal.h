@@ -46,6 +46,8 @@ struct DevPlan {
   const float* dtap;       // [4r - 1] decimation taps d_n, n = -(2r-1) .. 2r-1
   const int4* fbox;        // [m][forward block rows][forward block columns] image box of each
                            // forward block: (x0, y0, width, height), width 0 if no sample in D
+  const int* ftiles;       // forward tiles (indices into fbox): ftiles_small that fit the small
+  int ftiles_small, ftiles_large;  // patch (or have no sample in D), then the others
   // splat passes of the adjoint (geometry only, built at plan time), see adjoint.hip
   int adj_ntx;             // tiles per image row
   const int* adj_off;      // [tiles + 1] first pass of each tile
@@ -120,6 +122,8 @@ constexpr int theta_k1(int k_theta) { return k_theta <= 32 ? k_theta : 32; }
 // Plan time (host): image boxes of the forward blocks, in the order of the forward grid.
 std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& cs,
                                   const std::vector<int2>& fq, const std::vector<double>& erho);
+// Plan time (host): the forward's tile lists (small-patch tiles first; their count in *n_small).
+std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small);
 // The operator chains behind radon_fwd and radon_adj / radon_transpose / fbp (arguments
 // checked by the caller; ws holds workspace_layout(plan, batch, RL_OP_FWD or op)).
 rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int batch, void* ws, int stop_stage,
