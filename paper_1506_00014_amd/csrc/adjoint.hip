@@ -11,7 +11,8 @@
 //                  rows by the decimation filter and spread into LDS with the same 16
 //                  weights the forward gathers with; partitions are summed in the tile
 //   k_prefilter    (shared) Q is symmetric, times w_S / w_X
-//   k_ramp         Ram-Lak filter along s (sec. 6, eq. ramp) as a zero-padded real FFT
+//   k_ramp         FBP filter along s (sec. 6, eqs. ramp, cosfilt, SLfilt) as a zero-padded
+//                  real FFT times the filter's multiplier
 #include <hip/hip_runtime.h>
 
 #include "fft_device.h"

@@ -25,6 +25,8 @@ constexpr int kPSeg = 512;                 // output rows per block
 constexpr int kPRing = kPRB + 2 * kPrefR;  // row-filtered rows kept (64, a power of two)
 constexpr int kPGroups = kPRB * kPSI / 4;  // float4 groups of input per step (768)
 static_assert(kPGroups % kThreads == 0, "whole groups per thread");
+static_assert(kPRB * (kPSW / 8) == kThreads && kPSW * (kPRB / 8) == kThreads,
+              "one run of 8 outputs per thread in each filter pass");
 
 // Block: a strip of kPSW columns and up to kPSeg rows of one slice, streamed down in steps
 // of kPRB rows.  A step row-filters kPRB new input rows (the periodic 2 kPrefR + 1 taps,
