@@ -204,10 +204,12 @@ __global__ __launch_bounds__(256) void k_tau_table(DevPlan P, int2* __restrict__
   for (int k = threadIdx.x; k < P.n_s; k += blockDim.x) {
     double s = -1.0 + k * P.ds;
     if (wrap) s = -s;
-    const double tau = (log(aR * s + (1.0 - aR) * cth) - P.rho0) / P.d_rho;
+    // On the rows at theta' = +-beta/2 the edge sample lands on tau = -1 exactly, which rounding
+    // can put just below -1.  Clamping tau itself (not only its floor) keeps the base index and
+    // the fraction consistent, so the four taps stay where the unrounded tau puts them.
+    const double tau = fmin(fmax((log(aR * s + (1.0 - aR) * cth) - P.rho0) / P.d_rho, -1.0), (double)P.n_rho);
     const double ft = floor(tau);
-    const int kq = (int)fmin(fmax(ft, -1.0), (double)P.n_rho);
-    row[k] = make_int2(kq, __float_as_int((float)(tau - ft)));
+    row[k] = make_int2((int)ft, __float_as_int((float)(tau - ft)));
   }
 }
 

@@ -75,6 +75,30 @@ BIG_CASES = [
 ]
 
 
+# M = 5, 6, 8 (beta = pi/M) with rows at theta' = -beta/2 exactly, where the ray is tangent to D and
+# the sample at s = -1 lands on tau = -1 up to rounding (just below it at these sizes)
+TANGENT_CASES = [(128, 192, 128, 5), (128, 192, 128, 6), (128, 180, 128, 6), (128, 192, 128, 8)]
+
+
+@pytest.mark.parametrize("case", TANGENT_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
+def test_more_partitions_parity(dev, case):
+    """More partitions than the default, on geometries whose tangent rows put tau just below -1."""
+    n, nt, ns, m = case
+    plan, og = get_plan(n, nt, ns, m)
+    img, _ = inputs.ellipse_phantom(n, 8, 103)
+    got = plan.forward(to_dev(img, dev)).cpu().numpy()
+    ref = oradon.radon_fwd(og, f32(img))
+    e = rel(got, ref)
+    print(f"R M={m}: rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
+    g = inputs.normal_array((og.n_theta, og.n_s), 104)
+    got = plan.adjoint(to_dev(g, dev)).cpu().numpy()
+    ref = oradon.radon_adj(og, f32(g))
+    e = rel(got, ref)
+    print(f"R# M={m}: rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
+
+
 @pytest.mark.parametrize("case", BIG_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
 def test_forward_adjoint_parity_large(dev, case):
     n, nt, ns, m, kw = case

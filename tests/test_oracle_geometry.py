@@ -78,3 +78,21 @@ def test_defaults_respect_bounds():
         assert g.dtheta / g.r_dec <= 2 * g.a_R / n + 1e-15
     g = make_geometry(2048, 2048, 2048)
     assert (g.n_rho, g.k_theta, g.r_dec, g.n_own) == (4096, 1024, 6, 512)
+
+
+@pytest.mark.parametrize("n,n_theta,m", [(128, 192, 5), (128, 192, 6), (128, 180, 6), (128, 192, 8), (128, 180, 4)])
+def test_tau_range_is_one_period_plus_one_node(n, n_theta, m):
+    # On a line of the sector, a_R s + (1 - a_R) cos theta' lies in [a_r, 1]: its minimum is at
+    # s = -1 on the tangent rays theta' = +-beta/2 (eq. aconst), its maximum at s = 1, theta' = 0.
+    # With rho_0 = (1 - N_rho) d_rho and d_rho = -log(a_r) / N_rho that is tau in [-1, N_rho - 1].
+    from oracle import radon
+
+    g = make_geometry(n, n_theta, n, m=m)
+    lo, hi = np.inf, -np.inf
+    for p in range(m):
+        for _, j, tau in radon.eval_taus(g, p):
+            lo, hi = min(lo, tau.min()), max(hi, tau.max())
+            _, wrap, nu = g.owner(j)
+            if nu * 2 == -n_theta and not wrap:  # theta' = -beta/2: the sample at s = -1 sits on
+                assert abs(tau[0] + 1.0) < 1e-12  # tau = -1 (a wrapped row samples s = +1 - ds)
+    assert lo >= -1.0 - 1e-12 and hi <= g.n_rho - 1 + 1e-12
