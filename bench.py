@@ -188,6 +188,31 @@ def em_detail(plan, f, sino, B, reps, time_op, detail, log):
     log(f"EM step: {detail['per_op']['EM step']}")
 
 
+def m_sweep_detail(n, time_op, log, batch=16, seed=405):
+    """R and R# on `batch` slices of n x n (n angles x n bins) for M = 3, 4, 6, 8 partitions:
+    M sets the other geometry fields (N_rho, K, r) through rl_geom_default."""
+    import torch
+    from paper_1506_00014_amd import RadonPlan, _lib
+
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    f = torch.rand(batch, n, n, device="cuda", generator=gen)
+    out = {}
+    for m in (3, 4, 6, 8):
+        plan = RadonPlan(n, n, n, m=m)
+        ws = torch.empty(max(plan.workspace_bytes(batch, op) for op in (_lib.RL_OP_FWD, _lib.RL_OP_ADJ)),
+                         dtype=torch.uint8, device="cuda")
+        g = plan.forward(f, ws)
+        tf = time_op(lambda: plan.forward(f, ws), 3)
+        ta = time_op(lambda: plan.adjoint(g, ws), 3)
+        geo = plan.geom
+        out[str(m)] = {"n_rho": geo["n_rho"], "k_theta": geo["k_theta"], "r_dec": geo["r_dec"],
+                       "R_slices_per_s": round(batch / (tf / 1000.0), 1),
+                       "R#_slices_per_s": round(batch / (ta / 1000.0), 1)}
+        log(f"M={m}: {out[str(m)]}")
+        del plan, ws, g
+    return out
+
+
 def ragged_detail(torch, log, count=256, seed=401):
     """Ragged batch: `count` slices with N drawn from {256, 512, 768, 1024} (N x N sinograms),
     R and R# for the whole set as one replay of a captured graph vs one plain call per slice."""
@@ -252,6 +277,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch detail measurement")
+    ap.add_argument("--no-m-sweep", action="store_true",
+                    help="skip the R / R# rates at M = 3, 4, 6, 8 partitions")
     ap.add_argument("--no-em", action="store_true",
                     help="skip the EM step measurement (its normalisation is a batch-1 back-projection)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -382,6 +409,8 @@ def main():
     # EM reconstruction: one step (R, ratio, R#, update) on the whole batch
     if not args.no_em:
         em_detail(plan, f, sino, B, reps, time_op, detail, log)
+    if not args.no_m_sweep:
+        detail["m_sweep"] = m_sweep_detail(n, time_op, log)
     if not args.no_ragged:
         detail["ragged_batch"] = ragged_detail(torch, log)
     detail["paper_context"] = ("GTX 770, CUDA 7, FP32, M=3, N_theta=1.5N: EM 100 steps on 2048 slices of 2048^2 "
