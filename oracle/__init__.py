@@ -18,6 +18,9 @@ Modules
             multiplier H = zeta_hat / (B_hat_rho * D_hat_theta)
   radon     Algorithm 1 (fast Radon transform) step by step, its exact
             weighted transpose (the back-projection), and FBP (eq. FBP, ramp)
+  bp        Algorithm 2 (fast back-projection) step by step: sinogram spline
+            coefficients, lattice samples, convolution with zeta# (eq.
+            exprcoef2), bicubic gather to the image; FBP through it
   em        EM reconstruction step (sec. 7) on radon_fwd / radon_adj
   analytic  closed-form Radon transforms (disc, Gaussian, ellipse) used as pins
   brute     brute-force line integrals of the spline interpolant (pin)
