@@ -395,6 +395,9 @@ def main():
         "FBP": (lambda: plan.fbp(sino, ws), lambda i: plan.fbp(sino[i], ws1)),
         "FBP cosine": (lambda: plan.fbp(sino, ws, filter="cosine"), None),
         "FBP shepp-logan": (lambda: plan.fbp(sino, ws, filter="shepp-logan"), None),
+        # the paper's fast back-projection (Algorithm 2) and FBP through it
+        "R# (Alg. 2)": (lambda: plan.bp_lp(sino, ws), lambda i: plan.bp_lp(sino[i], ws1)),
+        "FBP (Alg. 2)": (lambda: plan.fbp_lp(sino, ws), lambda i: plan.fbp_lp(sino[i], ws1)),
     }
     detail = {"per_op": {}, "kernels": kernels}
     for op, (batched, single) in ops.items():

@@ -51,8 +51,16 @@ typedef enum {
   RL_ERR_INTERNAL = 6
 } rl_status;
 
-/* Operation selector for rl_workspace_bytes (RL_OP_EM: rl_em and, with batch 1, rl_em_norm). */
-typedef enum { RL_OP_FWD = 0, RL_OP_ADJ = 1, RL_OP_FBP = 2, RL_OP_EM = 3 } rl_op;
+/* Operation selector for rl_workspace_bytes (RL_OP_EM: rl_em and, with batch 1, rl_em_norm;
+ * RL_OP_BP_LP: radon_bp_lp; RL_OP_FBP_LP: fbp_lp). */
+typedef enum {
+  RL_OP_FWD = 0,
+  RL_OP_ADJ = 1,
+  RL_OP_FBP = 2,
+  RL_OP_EM = 3,
+  RL_OP_BP_LP = 4,
+  RL_OP_FBP_LP = 5
+} rl_op;
 
 /* Filters of filtered back-projection (sec. 6, eqs. ramp, cosfilt, SLfilt).  The ramp
  * is the Ram-Lak kernel; cosine and Shepp-Logan multiply the ramp's spectrum on the
@@ -152,6 +160,35 @@ rl_status radon_transpose(const rl_plan* plan, const float* d_sino, float* d_img
  * returns RL_ERR_INVALID_ARG before any launch. */
 rl_status fbp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch,
               rl_filter filter, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Back-projection by the paper's fast algorithm (sec. 5, Algorithm 2; kernel sec. 3 eq.
+ * exprcoef2), an approximation of the same integral R# g(x) = int_0^pi g(theta, x.theta)
+ * d theta that radon_adj computes as the exact weighted transpose of radon_fwd; the two agree
+ * to the method's discretisation error, not to rounding.  Per partition m:
+ *   1. spline coefficients of each sinogram row along s, the row extended by zeros beyond
+ *      its n_s samples (the lattice rows below lie on sinogram rows, so the prefilter in
+ *      theta followed by evaluation there is the identity);
+ *   2. the cubic spline of the row at the coarse log-polar lattice: lattice row theta'_i
+ *      (the rows m owns), column rho_q, line offset s = (e^rho_q - (1 - a_R) cos theta'_i)/a_R
+ *      (negated on rows that wrap past pi); no e^rho weight;
+ *   3. periodic convolution on the K x N_rho lattice with zeta#, whose Fourier coefficients
+ *      int_{-beta}^{beta} e^{-2 pi i k_theta u / (K dtheta)} (cos u)^{2 pi i k_rho / L} du are
+ *      divided by B_hat(k_theta/K) B_hat(k_rho/N_rho) so the result is a spline-coefficient
+ *      lattice in both variables;
+ *   4. bicubic evaluation of that lattice at the log-polar coordinates of T_m x for every
+ *      pixel x with |x| < 1 (node coordinates x = -1 + i dx); pixels with |x| >= 1 are 0;
+ * summed over partitions.  d_sino [batch][n_theta][n_s] -> d_img [batch][n][n], row-major
+ * float32 on the plan's device; the output is overwritten.  Workspace:
+ * rl_workspace_bytes(plan, batch, RL_OP_BP_LP), 256-byte aligned, not overlapping the
+ * input or output.  Errors and batch == 0 as radon_adj. */
+rl_status radon_bp_lp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, void* d_ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* FBP through Algorithm 2 (sec. 6 eq. FBP with sec. 5 Algorithm 2): the filter of fbp, then
+ * radon_bp_lp.  Arguments and errors as fbp; workspace rl_workspace_bytes(plan, batch,
+ * RL_OP_FBP_LP). */
+rl_status fbp_lp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, rl_filter filter,
+                 void* d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* EM reconstruction (sec. 7, the EM iteration), on radon_fwd and radon_adj:
  *   f <- f R#( chi_C g / R f ) / R# chi_C,

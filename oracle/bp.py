@@ -160,7 +160,8 @@ def pixel_coords(geom, p):
     n = geom.n
     x1 = -1.0 + geom.dx * np.arange(n)
     X1, X2 = np.meshgrid(x1, x1)  # [iy, ix]: X1 = x_1 (columns), X2 = x_2 (rows)
-    inside = X1 * X1 + X2 * X2 < 1.0
+    k = 2 * np.arange(n) - n  # node i sits at x = (2i - n)/n: |x| < 1 decided exactly
+    inside = k[None, :] ** 2 + k[:, None] ** 2 < n * n
     mb = p * geom.beta
     a_R = geom.a_R
     # y = T_m x = a_R Rot(-m beta) x + (1 - a_R, 0)

@@ -31,9 +31,9 @@ def chi_c(geom) -> np.ndarray:
 
 def disc_mask(geom) -> np.ndarray:
     """Pixels x with |x| < 1 (node coordinates), the support of the EM image."""
-    x = geom.x_nodes()
-    X1, X2 = np.meshgrid(x, x)
-    return X1 ** 2 + X2 ** 2 < 1.0
+    # node i sits at x = (2i - n)/n: decide |x| < 1 exactly in integers
+    k = 2 * np.arange(geom.n) - geom.n
+    return k[None, :] ** 2 + k[:, None] ** 2 < geom.n ** 2
 
 
 def em_norm(geom, mode="fft") -> np.ndarray:

@@ -5,7 +5,8 @@ The operators run in hand-written HIP kernels behind the C-ABI library libradonl
 does not load the library; the first plan does, and fails loudly if it is missing.
 """
 
-__all__ = ["RadonPlan", "radon_fwd", "radon_adj", "radon_transpose", "fbp", "RadonFn", "radon", "RaggedBatch"]
+__all__ = ["RadonPlan", "radon_fwd", "radon_adj", "radon_transpose", "fbp", "radon_bp_lp", "fbp_lp", "RadonFn", "radon",
+           "RaggedBatch"]
 
 
 def __getattr__(name):

@@ -22,7 +22,7 @@ STATUS_NAMES = {
     5: "RL_ERR_UNSUPPORTED_ARCH",
     6: "RL_ERR_INTERNAL",
 }
-RL_OP_FWD, RL_OP_ADJ, RL_OP_FBP, RL_OP_EM = 0, 1, 2, 3
+RL_OP_FWD, RL_OP_ADJ, RL_OP_FBP, RL_OP_EM, RL_OP_BP_LP, RL_OP_FBP_LP = 0, 1, 2, 3, 4, 5
 RL_FILTER_RAMLAK = 0
 RL_FILTER_COSINE = 1
 RL_FILTER_SHEPP_LOGAN = 2
@@ -41,6 +41,8 @@ EXPORTED = (
     "radon_adj",
     "radon_transpose",
     "fbp",
+    "radon_bp_lp",
+    "fbp_lp",
     "rl_last_error",
     "rl_debug_stage",
     "rl_profile_start",
@@ -106,12 +108,14 @@ def load(path: str = LIB_PATH):
     lib.rl_workspace_bytes.restype = c_size_t
     lib.rl_plan_samples.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int64)]
     lib.rl_plan_samples.restype = c_int32
-    for name in ("radon_fwd", "radon_adj", "radon_transpose"):
+    for name in ("radon_fwd", "radon_adj", "radon_transpose", "radon_bp_lp"):
         f = getattr(lib, name)
         f.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]
         f.restype = c_int32
-    lib.fbp.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_size_t, c_void_p]
-    lib.fbp.restype = c_int32
+    for name in ("fbp", "fbp_lp"):
+        f = getattr(lib, name)
+        f.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_size_t, c_void_p]
+        f.restype = c_int32
     lib.rl_last_error.argtypes = []
     lib.rl_last_error.restype = ctypes.c_char_p
     lib.rl_debug_stage.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]

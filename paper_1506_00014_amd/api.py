@@ -122,6 +122,20 @@ class RadonPlan:
         sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
         return self._run("fbp", sino, (g["n"], g["n"]), _lib.RL_OP_FBP, ws, extra=(_lib.FILTERS[filter],))
 
+    def bp_lp(self, sino, ws=None):
+        """R# g by the paper's Algorithm 2 (radon_bp_lp): [..., n_theta, n_s] -> [..., n, n]."""
+        g = self.geom
+        sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
+        return self._run("radon_bp_lp", sino, (g["n"], g["n"]), _lib.RL_OP_BP_LP, ws)
+
+    def fbp_lp(self, sino, ws=None, filter="ramlak"):
+        """FBP through Algorithm 2 (fbp_lp): the filter of fbp, then bp_lp."""
+        if filter not in _lib.FILTERS:
+            raise ValueError(f"unknown filter {filter!r}; one of {sorted(_lib.FILTERS)}")
+        g = self.geom
+        sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
+        return self._run("fbp_lp", sino, (g["n"], g["n"]), _lib.RL_OP_FBP_LP, ws, extra=(_lib.FILTERS[filter],))
+
     def em_norm(self, ws=None):
         """R# chi_C, the normalisation of the EM step: [n, n] (rl_em_norm)."""
         g = self.geom
@@ -208,6 +222,14 @@ def radon_transpose(plan: RadonPlan, sino, ws=None):
 
 def fbp(plan: RadonPlan, sino, ws=None, filter="ramlak"):
     return plan.fbp(sino, ws, filter=filter)
+
+
+def radon_bp_lp(plan: RadonPlan, sino, ws=None):
+    return plan.bp_lp(sino, ws)
+
+
+def fbp_lp(plan: RadonPlan, sino, ws=None, filter="ramlak"):
+    return plan.fbp_lp(sino, ws, filter=filter)
 
 
 class RadonFn(torch.autograd.Function):

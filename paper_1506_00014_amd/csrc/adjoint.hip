@@ -748,6 +748,10 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
+}  // namespace
+
+namespace rl {
+
 rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int batch, void* ws, size_t ws_bytes,
                      rl_op op) {
   if (!plan) return fail(RL_ERR_INVALID_ARG, "plan is NULL");
@@ -766,9 +770,6 @@ rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int b
   return check_plan_device(plan);
 }
 
-}  // namespace
-
-namespace rl {
 
 rl_status adjoint_chain(const rl_plan* plan, const float* sino, float* img, int batch, void* ws, rl_op op,
                         bool transpose, hipStream_t s) {

@@ -1,0 +1,194 @@
+// Back-projection by the paper's fast algorithm (sec. 5, Algorithm 2), and FBP through it.
+//
+//   k_bp_rows_rfft  one owned lattice row per block: the sinogram row's spline coefficients
+//                   along s (FIR sqrt(3) z^|k|, the row extended by zeros), the cubic spline
+//                   at the row's log-polar columns (s = (e^rho - (1 - a_R) cos theta')/a_R,
+//                   Alg. 2 step 3), then a real FFT along rho
+//   k_theta_conv    (shared) with the multiplier H# = zeta#_hat / (B_hat_theta B_hat_rho)
+//                   (Alg. 2 step 4, eq. exprcoef2), owned rows in, support rows out
+//   k_irfft_rows    (shared) inverse real FFT along rho of every support row
+//   k_bp_gather     one thread per pixel: for each partition the bicubic spline of the
+//                   lattice at the log-polar coordinates of T_m x (Alg. 2 step 5), summed
+//                   over partitions (step 7); pixels with |x| >= 1 are zero
+//   k_ramp          (shared) the FBP filter, before k_bp_rows_rfft
+#include <hip/hip_runtime.h>
+
+#include "fft_device.h"
+#include "rl_internal.h"
+
+namespace rl {
+
+namespace {
+
+// Coefficients are kept on k = -kBpPad .. n_s + kBpPad - 1: the truncated FIR reaches kPrefR
+// samples past the row, and the 4-tap evaluation two more.
+constexpr int kBpPad = kPrefR + 2;
+constexpr int kGx = 16, kGy = 16;  // pixels per gather block (kGx * kGy == kThreads)
+static_assert(kGx * kGy == kThreads, "one pixel per thread");
+
+size_t bp_rows_lds(const DevPlan& d) {
+  return (size_t)(d.n_rho + 2 * (d.n_s + 2 * kBpPad)) * sizeof(float);
+}
+
+}  // namespace
+
+// Block: owned row o of one (slice, partition); writes the row's rho half-spectrum.
+__global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const float* __restrict__ sino,
+                                                           float2* __restrict__ spec) {
+  extern __shared__ float2 sh[];
+  const int nc = P.nc, nr = P.n_rho, ns = P.n_s;
+  const int o = blockIdx.x;
+  const int bm = blockIdx.y;
+  const int b = bm / P.m, m = bm - b * P.m;
+  const int jw = P.own_j[m * P.n_own + o];
+  float2* dst = spec + ((size_t)bm * P.n_own + o) * P.ld;
+  if (jw < 0) {  // uniform across the block
+    for (int k = threadIdx.x; k <= nc; k += blockDim.x) dst[k] = make_float2(0.f, 0.f);
+    return;
+  }
+  const int j = jw & ((1 << 30) - 1);
+  const bool wrap = (jw >> 30) & 1;
+  float* x = reinterpret_cast<float*>(sh);  // [n_rho] the lattice row, then its FFT
+  const int nw = ns + 2 * kBpPad;
+  float* gs = x + nr;   // [nw] the sinogram row at index k + kBpPad, zeros outside
+  float* cs = gs + nw;  // [nw] its spline coefficients, same indexing
+  const float* src = sino + ((size_t)b * P.n_theta + j) * ns;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+    const int k = i - kBpPad;
+    gs[i] = (k >= 0 && k < ns) ? src[k] : 0.f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+    float acc = P.pref[0] * gs[i];
+    for (int d = 1; d <= kPrefR; ++d) {
+      const float l = i - d >= 0 ? gs[i - d] : 0.f;
+      const float r = i + d < nw ? gs[i + d] : 0.f;
+      acc += P.pref[d] * (l + r);
+    }
+    cs[i] = acc;
+  }
+  __syncthreads();
+  const double cth = P.own_cos[m * P.n_own + o];
+  const double c0 = (1.0 - P.a_R) * cth, e_scale = P.a_R * P.dx, inv_aR = 1.0 / P.a_R;
+  const double inv_ds = 1.0 / P.ds;
+  for (int q = threadIdx.x; q < nr; q += blockDim.x) {
+    double s = (P.erho[q] * e_scale - c0) * inv_aR;  // line offset of lattice node (theta', rho_q)
+    if (wrap) s = -s;
+    const double t = (s + 1.0) * inv_ds;  // index position along s
+    float v = 0.f;
+    // taps beyond the stored coefficients are zero; the range test also keeps the integer
+    // conversion below in range for any t
+    if (t > -(double)kBpPad - 2.0 && t < (double)(ns + kBpPad + 1)) {
+      const double ft = floor(t);
+      const int k0 = (int)ft + kBpPad;
+      float w[4];
+      bspline_w6((float)(t - ft), w);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int idx = k0 - 1 + a;
+        if (idx >= 0 && idx < nw) v += w[a] * cs[idx];
+      }
+      v *= (1.0f / 6.0f);
+    }
+    x[q] = v;
+  }
+  __syncthreads();
+  fft_lds<kRowVals, false>(sh, nc, 1, P.twp_rows);
+  rfft_post(sh, nc, P.tw, P.tw_len, [&](int k, float2 xv) { dst[k] = xv; });
+}
+
+// Block: 16 x 16 pixels of one slice.  lat holds the support rows [batch][m][n_sup][n_rho]
+// of the convolved lattice (spline coefficients); support row kHalo is a partition's first
+// owned row.
+__global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* __restrict__ lat,
+                                                        float* __restrict__ img) {
+  const int ix = blockIdx.x * kGx + (int)(threadIdx.x % kGx);
+  const int iy = blockIdx.y * kGy + (int)(threadIdx.x / kGx);
+  const int b = blockIdx.z;
+  if (ix >= P.n || iy >= P.n) return;
+  const double x1 = -1.0 + ix * P.dx, x2 = -1.0 + iy * P.dx;
+  const int nr = P.n_rho;
+  float acc = 0.f;
+  if (in_unit_disc(ix, iy, P.n)) {
+    for (int m = 0; m < P.m; ++m) {
+      double sm, cm;
+      sincospi((double)m / (double)P.m, &sm, &cm);
+      // y = T_m x = a_R Rot(-m beta) x + (1 - a_R, 0) (eq. Tdef)
+      const double y1 = P.a_R * (cm * x1 + sm * x2) + (1.0 - P.a_R);
+      const double y2 = P.a_R * (cm * x2 - sm * x1);
+      const double T = (atan2(y2, y1) - P.phi0[m]) / P.dtheta;
+      const double R = (0.5 * log(y1 * y1 + y2 * y2) - P.rho0) / P.d_rho;
+      const double ft = floor(T), fr = floor(R);
+      float wt[4], wr[4];
+      bspline_w6((float)(T - ft), wt);
+      bspline_w6((float)(R - fr), wr);
+      // |x| < 1 puts T in [1, n_own + 2) and R in [-1, n_rho - 1] (T_m maps the unit disc
+      // onto D); the clamps only guard the loads
+      const int kt = min(max((int)ft, 1), P.n_sup - 3);
+      const int kr = min(max((int)fr, -1), nr - 1);
+      const float* L = lat + ((size_t)(b * P.m + m) * P.n_sup + (kt - 1)) * nr;
+      int col[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) col[c] = wrap1(kr - 1 + c, nr);
+      float v = 0.f;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const float* Lr = L + (size_t)a * nr;
+        v += wt[a] * (wr[0] * Lr[col[0]] + wr[1] * Lr[col[1]] + wr[2] * Lr[col[2]] + wr[3] * Lr[col[3]]);
+      }
+      acc += v;
+    }
+    acc *= (1.0f / 36.0f);
+  }
+  img[((size_t)b * P.n + iy) * P.n + ix] = acc;
+}
+
+rl_status prepare_bp_launches(const rl_plan* p) {
+  return ensure_dyn_lds((const void*)k_bp_rows_rfft, bp_rows_lds(p->d), "hipFuncSetAttribute(k_bp_rows_rfft)");
+}
+
+static rl_status bp_lp_chain(const rl_plan* plan, const float* sino, float* img, int batch, void* ws, rl_op op,
+                             hipStream_t s) {
+  const DevPlan& d = plan->d;
+  const WsLayout L = workspace_layout(plan, batch, op);
+  char* w = (char*)ws;
+  float* U = (float*)(w + L.off[1]);
+  float2* Bs = (float2*)(w + L.off[2]);
+  float2* A = (float2*)(w + L.off[3]);
+  rl_status st;
+  {
+    const size_t lds = bp_rows_lds(d);
+    if ((st = ensure_dyn_lds((const void*)k_bp_rows_rfft, lds, "hipFuncSetAttribute(k_bp_rows_rfft)")) != RL_OK)
+      return st;
+    RL_LAUNCH("k_bp_rows_rfft", k_bp_rows_rfft, dim3(d.n_own, batch * d.m), dim3(kThreads), lds, s, d, sino, A);
+    if ((st = check_launch("k_bp_rows_rfft")) != RL_OK) return st;
+  }
+  if ((st = launch_theta_conv(plan, A, d.n_own, kHalo, Bs, d.n_sup, 0, false, batch, s, d.Hbp)) != RL_OK) return st;
+  if ((st = launch_irfft_rows(plan, Bs, U, batch * d.m * d.n_sup, s)) != RL_OK) return st;
+  dim3 grid((d.n + kGx - 1) / kGx, (d.n + kGy - 1) / kGy, batch);
+  RL_LAUNCH("k_bp_gather", k_bp_gather, grid, dim3(kThreads), 0, s, d, U, img);
+  return check_launch("k_bp_gather");
+}
+
+}  // namespace rl
+
+using namespace rl;
+
+extern "C" rl_status radon_bp_lp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, void* d_ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+  rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_BP_LP);
+  if (st != RL_OK || batch == 0) return st;
+  return bp_lp_chain(plan, d_sino, d_img, batch, d_ws, RL_OP_BP_LP, stream);
+}
+
+extern "C" rl_status fbp_lp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, rl_filter filter,
+                            void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  if (filter != RL_FILTER_RAMLAK && filter != RL_FILTER_COSINE && filter != RL_FILTER_SHEPP_LOGAN)
+    return fail(RL_ERR_INVALID_ARG, "unknown filter");
+  rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_FBP_LP);
+  if (st != RL_OK || batch == 0) return st;
+  const WsLayout L = workspace_layout(plan, batch, RL_OP_FBP_LP);
+  float* wg = (float*)((char*)d_ws + L.off[4]);
+  if ((st = launch_ramp(plan, d_sino, wg, batch, (int)filter, stream)) != RL_OK) return st;
+  return bp_lp_chain(plan, wg, d_img, batch, d_ws, RL_OP_FBP_LP, stream);
+}

@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <string>
 
+#include "fft_device.h"
 #include "rl_internal.h"
 
 namespace rl {
@@ -35,14 +36,12 @@ __global__ __launch_bounds__(kEThreads) void k_em_ratio(const float* __restrict_
 }
 
 __global__ __launch_bounds__(kEThreads) void k_em_update(float* __restrict__ f, const float* __restrict__ back,
-                                                         const float* __restrict__ norm, size_t count, int n,
-                                                         double dx) {
+                                                         const float* __restrict__ norm, size_t count, int n) {
   const size_t nn = (size_t)n * n;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
     const size_t p = i % nn;
-    const double x1 = -1.0 + (double)(p % n) * dx, x2 = -1.0 + (double)(p / n) * dx;
     const float w = norm[p];
-    f[i] = (x1 * x1 + x2 * x2 < 1.0 && w > 0.f) ? f[i] * back[i] / w : 0.f;
+    f[i] = (in_unit_disc((int)(p % n), (int)(p / n), n) && w > 0.f) ? f[i] * back[i] / w : 0.f;
   }
 }
 
@@ -133,7 +132,7 @@ extern "C" rl_status rl_em(const rl_plan* plan, const float* d_sino, const float
     hipLaunchKernelGGL(k_em_ratio, grid_for(cs), dim3(kEThreads), 0, stream, d_sino, rf, cs, d.n_s, d.ds);
     if ((st = check_launch("k_em_ratio")) != RL_OK) return st;
     if ((st = adjoint_chain(plan, rf, back, batch, w + L.chain, RL_OP_ADJ, false, stream)) != RL_OK) return st;
-    hipLaunchKernelGGL(k_em_update, grid_for(ci), dim3(kEThreads), 0, stream, d_img, back, d_norm, ci, d.n, d.dx);
+    hipLaunchKernelGGL(k_em_update, grid_for(ci), dim3(kEThreads), 0, stream, d_img, back, d_norm, ci, d.n);
     if ((st = check_launch("k_em_update")) != RL_OK) return st;
   }
   return RL_OK;

@@ -257,6 +257,13 @@ __device__ __forceinline__ void bspline_w6(float a, float* w) {
   w[3] = a3;
 }
 
+// Image node (ix, iy) lies strictly inside the unit disc: its coordinates are (2i - n)/n, so the
+// test is exact in integers (floating point could round nodes with |x| = 1 either way).
+__device__ __forceinline__ bool in_unit_disc(int ix, int iy, int n) {
+  const long long a = 2LL * ix - n, b = 2LL * iy - n;
+  return a * a + b * b < (long long)n * n;
+}
+
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // Blocks are dispatched to the chip's 8 XCDs (each with its own L2) round-robin by linear

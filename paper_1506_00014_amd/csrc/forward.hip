@@ -623,8 +623,10 @@ rl_status prepare_forward_launches(const rl_plan* p) {
 
 template <int K1, int K2>
 static rl_status launch_theta_conv_t(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out,
-                                     int out_rows, int out_off, bool conj, int batch, hipStream_t s) {
-  const DevPlan& d = p->d;
+                                     int out_rows, int out_off, bool conj, int batch, hipStream_t s,
+                                     const float2* H) {
+  DevPlan d = p->d;
+  if (H) d.H = H;
   const int cw = theta_cw<K1, K2>();
   const size_t lds = theta_lds<K1, K2>();
   rl_status st = ensure_dyn_lds((const void*)k_theta_conv<K1, K2>, lds, "hipFuncSetAttribute(k_theta_conv)");
@@ -636,17 +638,17 @@ static rl_status launch_theta_conv_t(const rl_plan* p, const float2* in, int in_
 }
 
 rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out, int out_rows,
-                            int out_off, bool conj, int batch, hipStream_t s) {
+                            int out_off, bool conj, int batch, hipStream_t s, const float2* H) {
   switch (p->d.k_theta) {
-    case 8: return launch_theta_conv_t<8, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
-    case 16: return launch_theta_conv_t<16, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
-    case 32: return launch_theta_conv_t<32, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
-    case 64: return launch_theta_conv_t<32, 2>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
-    case 128: return launch_theta_conv_t<32, 4>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
-    case 256: return launch_theta_conv_t<32, 8>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
-    case 512: return launch_theta_conv_t<32, 16>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
-    case 1024: return launch_theta_conv_t<32, 32>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
-    case 2048: return launch_theta_conv_t<32, 64>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s);
+    case 8: return launch_theta_conv_t<8, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
+    case 16: return launch_theta_conv_t<16, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
+    case 32: return launch_theta_conv_t<32, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
+    case 64: return launch_theta_conv_t<32, 2>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
+    case 128: return launch_theta_conv_t<32, 4>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
+    case 256: return launch_theta_conv_t<32, 8>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
+    case 512: return launch_theta_conv_t<32, 16>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
+    case 1024: return launch_theta_conv_t<32, 32>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
+    case 2048: return launch_theta_conv_t<32, 64>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
     default: return fail(RL_ERR_INTERNAL, "unsupported k_theta");
   }
 }

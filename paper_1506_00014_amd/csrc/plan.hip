@@ -298,7 +298,8 @@ WsLayout workspace_layout(const rl_plan* plan, int batch, rl_op op) {
       sizes[1] = lp;        // log-polar adjoint samples
       sizes[2] = spec_sup;  // convolved spectra of the support rows
       sizes[3] = spec_own;  // rho spectra of the owned rows
-      if (op == RL_OP_FBP) sizes[4] = sino;  // ramp-filtered sinogram
+      if (op == RL_OP_FBP || op == RL_OP_FBP_LP) sizes[4] = sino;  // filtered sinogram
+      if (op == RL_OP_BP_LP || op == RL_OP_FBP_LP) sizes[0] = 0;  // Algorithm 2 writes the image directly
     }
   }
   size_t off = 0;
@@ -507,7 +508,10 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   const int n_panels = std::max(8, (int)std::ceil(2.0 * d.beta * max_rate / 6.0));
   int n_nodes = n_panels * 16;
   const int n_nodes_pad = (n_nodes + kZN - 1) / kZN * kZN;
+  // zeta_hat (eq. exprcoef1): amplitude w / cos u, phase log cos u; zeta#_hat (eq. exprcoef2):
+  // amplitude w, phase -log cos u (the integrand's (cos u)^{2 pi i k_rho / L})
   std::vector<double> u(n_nodes_pad, 0.0), amp(n_nodes_pad, 0.0), lcv(n_nodes_pad, 0.0);
+  std::vector<double> amp2(n_nodes_pad, 0.0), lcv2(n_nodes_pad, 0.0);
   const double hw = d.beta / n_panels;
   for (int pi = 0; pi < n_panels; ++pi) {
     const double mid = -d.beta + (2.0 * pi + 1.0) * hw;
@@ -516,6 +520,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
       u[pi * 16 + i] = x;
       amp[pi * 16 + i] = hw * wg[i] / std::cos(x);
       lcv[pi * 16 + i] = std::log(std::cos(x));
+      amp2[pi * 16 + i] = hw * wg[i];
+      lcv2[pi * 16 + i] = -std::log(std::cos(x));
     }
   }
 
@@ -523,6 +529,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   size_t off = 0;
   const size_t o_H = off; off += al(sizeof(float2) * (size_t)nkr * nkt);
+  const size_t o_Hb = off; off += al(sizeof(float2) * (size_t)nkr * nkt);
   const size_t o_cs = off; off += al(sizeof(double2) * fine_cs.size());
   const size_t o_q = off; off += al(sizeof(int2) * fine_q.size());
   const size_t o_dec = off; off += al(sizeof(float4) * dec.size());
@@ -541,12 +548,13 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   const size_t o_ft = off; off += al(sizeof(int) * ftiles.size());
   const size_t table_bytes = off;
   // scratch for the quadrature (freed before returning)
-  const size_t s_u = 0, s_a = al(sizeof(double) * n_nodes_pad), s_l = 2 * s_a, s_z = 3 * s_a;
-  const size_t scratch = s_z + al(sizeof(double2) * (size_t)nkt * nkr);
+  const size_t s_u = 0, s_a = al(sizeof(double) * n_nodes_pad), s_l = 2 * s_a, s_a2 = 3 * s_a, s_l2 = 4 * s_a;
+  const size_t s_z = 5 * s_a, s_z2 = s_z + al(sizeof(double2) * (size_t)nkt * nkr);
+  const size_t scratch = s_z2 + al(sizeof(double2) * (size_t)nkt * nkr);
 
   char* mem = nullptr;
   char* tmp = nullptr;
-  std::vector<double2> zeta((size_t)nkt * nkr);
+  std::vector<double2> zeta((size_t)nkt * nkr), zeta2((size_t)nkt * nkr);
   auto cleanup = [&](rl_status code) {
     if (tmp) (void)hipFree(tmp);
     if (code != RL_OK) {
@@ -560,14 +568,21 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   if ((st = check_hip(hipMemcpy(tmp + s_u, u.data(), sizeof(double) * n_nodes_pad, hipMemcpyHostToDevice), "copy nodes")) != RL_OK) return cleanup(st);
   if ((st = check_hip(hipMemcpy(tmp + s_a, amp.data(), sizeof(double) * n_nodes_pad, hipMemcpyHostToDevice), "copy weights")) != RL_OK) return cleanup(st);
   if ((st = check_hip(hipMemcpy(tmp + s_l, lcv.data(), sizeof(double) * n_nodes_pad, hipMemcpyHostToDevice), "copy logcos")) != RL_OK) return cleanup(st);
+  if ((st = check_hip(hipMemcpy(tmp + s_a2, amp2.data(), sizeof(double) * n_nodes_pad, hipMemcpyHostToDevice), "copy weights")) != RL_OK) return cleanup(st);
+  if ((st = check_hip(hipMemcpy(tmp + s_l2, lcv2.data(), sizeof(double) * n_nodes_pad, hipMemcpyHostToDevice), "copy logcos")) != RL_OK) return cleanup(st);
   {
     dim3 grid((nkt + kZT - 1) / kZT, (nkr + kZT - 1) / kZT);
     hipLaunchKernelGGL(k_zeta_hat, grid, dim3(256), 0, 0, (double2*)(tmp + s_z), (const double*)(tmp + s_u),
                        (const double*)(tmp + s_a), (const double*)(tmp + s_l), n_nodes_pad, nkt, nkr, 1.0 / P,
                        1.0 / L);
     if ((st = check_launch("k_zeta_hat")) != RL_OK) return cleanup(st);
+    hipLaunchKernelGGL(k_zeta_hat, grid, dim3(256), 0, 0, (double2*)(tmp + s_z2), (const double*)(tmp + s_u),
+                       (const double*)(tmp + s_a2), (const double*)(tmp + s_l2), n_nodes_pad, nkt, nkr, 1.0 / P,
+                       1.0 / L);
+    if ((st = check_launch("k_zeta_hat")) != RL_OK) return cleanup(st);
   }
   if ((st = check_hip(hipMemcpy(zeta.data(), tmp + s_z, sizeof(double2) * zeta.size(), hipMemcpyDeviceToHost), "copy zeta")) != RL_OK) return cleanup(st);
+  if ((st = check_hip(hipMemcpy(zeta2.data(), tmp + s_z2, sizeof(double2) * zeta2.size(), hipMemcpyDeviceToHost), "copy zeta#")) != RL_OK) return cleanup(st);
 
   // H = zeta_hat / (B_hat(kr/N_rho) D_hat(kt) K N_rho), stored [kr][kt]; real part at the rho Nyquist bin
   std::vector<float2> H((size_t)nkr * nkt);
@@ -591,12 +606,28 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
       }
     }
   }
+  // H# = zeta#_hat / (B_hat(kt/K) B_hat(kr/N_rho) K N_rho) (Alg. 2 step 4), same layout and
+  // Nyquist treatment
+  std::vector<float2> Hb((size_t)nkr * nkt);
+  {
+    const double norm = 1.0 / ((double)g.k_theta * g.n_rho);
+    for (int kr = 0; kr < nkr; ++kr) {
+      const double bh = 2.0 / 3.0 + std::cos(2.0 * M_PI * kr / g.n_rho) / 3.0;
+      for (int kt = 0; kt < nkt; ++kt) {
+        const double bt = 2.0 / 3.0 + std::cos(2.0 * M_PI * kt / g.k_theta) / 3.0;
+        const double2 z = zeta2[(size_t)kt * nkr + kr];
+        const double s = norm / (bh * bt);
+        Hb[(size_t)kr * nkt + kt] = make_float2((float)(z.x * s), kr == nkr - 1 ? 0.f : (float)(z.y * s));
+      }
+    }
+  }
   struct Up {
     size_t off;
     const void* src;
     size_t bytes;
   } ups[] = {
       {o_H, H.data(), sizeof(float2) * H.size()},
+      {o_Hb, Hb.data(), sizeof(float2) * Hb.size()},
       {o_cs, fine_cs.data(), sizeof(double2) * fine_cs.size()},
       {o_q, fine_q.data(), sizeof(int2) * fine_q.size()},
       {o_dec, dec.data(), sizeof(float4) * dec.size()},
@@ -617,6 +648,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
     if ((st = check_hip(hipMemcpy(mem + up.off, up.src, up.bytes, hipMemcpyHostToDevice), "upload table")) != RL_OK)
       return cleanup(st);
   d.H = (const float2*)(mem + o_H);
+  d.Hbp = (const float2*)(mem + o_Hb);
   d.fine_cs = (const double2*)(mem + o_cs);
   d.fine_q = (const int2*)(mem + o_q);
   d.dec = (const float4*)(mem + o_dec);
@@ -647,7 +679,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
     plan->d_mem = nullptr;  // freed by cleanup
     return cleanup(st);
   }
-  if ((st = prepare_forward_launches(plan)) != RL_OK || (st = prepare_adjoint_launches(plan)) != RL_OK) {
+  if ((st = prepare_forward_launches(plan)) != RL_OK || (st = prepare_adjoint_launches(plan)) != RL_OK ||
+      (st = prepare_bp_launches(plan)) != RL_OK) {
     if (plan->d_adj) (void)hipFree(plan->d_adj);
     plan->d_mem = nullptr;
     return cleanup(st);
@@ -679,7 +712,7 @@ extern "C" rl_status rl_plan_geometry(const rl_plan* plan, rl_geom* out) {
 extern "C" size_t rl_workspace_bytes(const rl_plan* plan, int32_t batch, rl_op op) {
   if (!plan || batch <= 0) return 0;
   if (op == RL_OP_EM) return em_workspace_bytes(plan, batch);
-  if (op != RL_OP_FWD && op != RL_OP_ADJ && op != RL_OP_FBP) return 0;
+  if (op != RL_OP_FWD && op != RL_OP_ADJ && op != RL_OP_FBP && op != RL_OP_BP_LP && op != RL_OP_FBP_LP) return 0;
   return workspace_layout(plan, batch, op).total;
 }
 

@@ -28,6 +28,7 @@ struct DevPlan {
   double X0[kMaxPart], Y0[kMaxPart];   // image index of T_m^{-1}(0) offsets, per partition
   double phi0[kMaxPart];               // theta' of support row 0, per partition
   const float2* H;         // [nc + 1][k_theta/2 + 1], zeta_hat/(B_hat D_hat K N_rho)
+  const float2* Hbp;       // [nc + 1][k_theta/2 + 1], zeta#_hat/(B_hat_theta B_hat_rho K N_rho)
   const double2* fine_cs;  // [m][n_fine] (cos(phi_t + m beta), sin(phi_t + m beta))
   const int2* fine_q;      // [m][n_fine] inclusive rho-index range inside D (lo > hi: empty)
   const float4* dec;       // [r] weights of the decimation filter for phase p
@@ -104,8 +105,10 @@ rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int ba
                            hipStream_t s);
 rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s);
 rl_status launch_rfft_rows(const rl_plan* p, const float* in, float2* out, int rows, hipStream_t s);
+// H: the multiplier table (nullptr: the plan's H of the Radon transform).
 rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out,
-                            int out_rows, int out_off, bool conj, int batch, hipStream_t s);
+                            int out_rows, int out_off, bool conj, int batch, hipStream_t s,
+                            const float2* H = nullptr);
 rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, float* sino, int batch,
                             hipStream_t s);
 rl_status launch_splat_rfft(const rl_plan* p, const float* sino, float2* spec, int batch,
@@ -130,6 +133,11 @@ rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int 
                         float* stage_out, hipStream_t s);
 rl_status adjoint_chain(const rl_plan* plan, const float* sino, float* img, int batch, void* ws, rl_op op,
                         bool transpose, hipStream_t s);
+// Argument checks shared by the sinogram -> image entry points (op selects the workspace).
+rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int batch, void* ws, size_t ws_bytes,
+                     rl_op op);
+// Plan time: raise the LDS limit of the Algorithm 2 row kernel (bp.hip).
+rl_status prepare_bp_launches(const rl_plan* p);
 // Workspace of rl_em / rl_em_norm (em.hip).
 size_t em_workspace_bytes(const rl_plan* plan, int batch);
 // Plan time: build the adjoint splat passes (allocates plan->d_adj, fills the adj_* fields).

@@ -1,0 +1,156 @@
+"""GPU parity of the paper's fast back-projection (Algorithm 2: radon_bp_lp, fbp_lp) through
+the C-ABI against the FP64 oracle (oracle/bp.py) on the same seeded inputs.  Bar: relative
+L2 <= 1e-5; the error against FP64 is printed for every case."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bp as obp  # noqa: E402
+from oracle import radon as oradon  # noqa: E402
+from oracle.geometry import Geometry  # noqa: E402
+from paper_1506_00014_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+_plans = {}
+
+
+def get_plan(n, nt, ns, m=4):
+    from paper_1506_00014_amd import RadonPlan
+
+    key = (n, nt, ns, m)
+    if key not in _plans:
+        p = RadonPlan(n, nt, ns, m=m)
+        g = p.geom
+        og = Geometry(g["n"], g["n_theta"], g["n_s"], g["m"], g["n_rho"], g["k_theta"], g["r_dec"]).validate()
+        _plans[key] = (p, og)
+    return _plans[key]
+
+
+def f32(x):
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+CASES = [
+    (128, 180, 128, 4),  # the 128 x 128, 180-angle configuration
+    (64, 90, 64, 4),
+    (100, 150, 100, 3),  # M = 3, N not a multiple of the 16-pixel gather block
+    (96, 97, 80, 5),     # odd N_theta, N_s != N
+    (128, 192, 128, 6),  # rows on the tangent rays theta' = -beta/2
+    (128, 192, 128, 8),
+    (16, 24, 16, 4),     # smaller than one gather block
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
+def test_bp_lp_parity(dev, case):
+    plan, og = get_plan(*case)
+    g = inputs.normal_array((og.n_theta, og.n_s), 601)
+    got = plan.bp_lp(torch.tensor(g.astype(np.float32), device=dev)).cpu().numpy()
+    ref = obp.radon_bp_lp(og, f32(g))
+    e = rel(got, ref)
+    print(f"bp_lp {case}: rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
+    # pixels with |x| >= 1 are exactly zero
+    x = -1 + og.dx * np.arange(og.n)
+    out = (x[None, :] ** 2 + x[:, None] ** 2) >= 1.0
+    assert np.all(got[out] == 0.0)
+
+
+@pytest.mark.parametrize("filt", ["ramlak", "cosine", "shepp-logan"])
+def test_fbp_lp_parity(dev, filt):
+    plan, og = get_plan(128, 180, 128, 4)
+    img, _ = inputs.ellipse_phantom(128, 8, 602)
+    sino = oradon.radon_fwd(og, f32(img))
+    got = plan.fbp_lp(torch.tensor(sino.astype(np.float32), device=dev), filter=filt).cpu().numpy()
+    ref = obp.fbp_lp(og, f32(sino), filt)
+    e = rel(got, ref)
+    print(f"fbp_lp {filt}: rel L2 vs FP64 oracle {e:.2e}; image error {rel(got, img):.3f}")
+    assert e <= TOL
+
+
+def test_bp_lp_batch_equals_singles(dev):
+    plan, og = get_plan(96, 97, 80, 5)
+    g = torch.tensor(np.stack([inputs.normal_array((og.n_theta, og.n_s), 610 + i) for i in range(3)]).astype(np.float32),
+                     device=dev)
+    both = plan.bp_lp(g).cpu().numpy()
+    for i in range(3):
+        one = plan.bp_lp(g[i]).cpu().numpy()
+        assert np.array_equal(both[i], one)
+    assert plan.bp_lp(g[:0]).shape == (0, og.n, og.n)
+
+
+def test_bp_lp_close_to_exact_transpose_on_smooth_data(dev):
+    # both approximate int_0^pi g(theta, x . theta) d theta; on a smooth sinogram they agree to
+    # the method's discretisation error
+    plan, og = get_plan(256, 256, 256, 4)
+    th = np.arange(og.n_theta) * og.dtheta
+    T, S = np.meshgrid(th, og.s_nodes(), indexing="ij")
+    g = np.exp(-((S - 0.3 * np.cos(T) + 0.1 * np.sin(T)) ** 2) / 0.02).astype(np.float32)
+    gd = torch.tensor(g, device=dev)
+    a = plan.bp_lp(gd).cpu().numpy()
+    b = plan.adjoint(gd).cpu().numpy()
+    e = rel(a, b)
+    print(f"bp_lp vs radon_adj on smooth data: {e:.2e}")
+    assert e < 2e-2
+
+
+def test_bp_lp_errors(dev):
+    from paper_1506_00014_amd import _lib
+
+    plan, og = get_plan(64, 90, 64, 4)
+    lib = _lib.load()
+    g = torch.zeros(og.n_theta, og.n_s, device=dev)
+    out = torch.empty(og.n, og.n, device=dev)
+    need = plan.workspace_bytes(1, _lib.RL_OP_BP_LP)
+    assert need > 0 and plan.workspace_bytes(1, _lib.RL_OP_FBP_LP) > need
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+
+    def p(t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    assert lib.radon_bp_lp(plan._ptr, p(g), p(out), 1, p(ws), need - 1, None) == _lib.RL_ERR_WORKSPACE
+    assert lib.radon_bp_lp(plan._ptr, None, p(out), 1, p(ws), need, None) == _lib.RL_ERR_INVALID_ARG
+    assert lib.radon_bp_lp(plan._ptr, p(g), p(out), -1, p(ws), need, None) == _lib.RL_ERR_INVALID_ARG
+    assert lib.radon_bp_lp(plan._ptr, p(g), p(out), 0, None, 0, None) == _lib.RL_OK
+    ws2 = torch.empty(plan.workspace_bytes(1, _lib.RL_OP_FBP_LP), dtype=torch.uint8, device=dev)
+    assert lib.fbp_lp(plan._ptr, p(g), p(out), 1, 7, p(ws2), ws2.numel(), None) == _lib.RL_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        plan.fbp_lp(g, filter="hann")
+
+
+def test_bp_lp_2048_batch64_sampled(dev):
+    # the 2048 x 2048 geometry (2048 angles x 2048 bins, M = 4) in the bench's launch
+    # configuration (batch 64): slice 37 against the oracle, slice 0 against a batch-1 call
+    plan, og = get_plan(2048, 2048, 2048, 4)
+    gen = torch.Generator(device=dev).manual_seed(620)
+    g = torch.randn(64, og.n_theta, og.n_s, device=dev, generator=gen)
+    from paper_1506_00014_amd import _lib
+
+    ws = torch.empty(plan.workspace_bytes(64, _lib.RL_OP_BP_LP), dtype=torch.uint8, device=dev)
+    out = plan.bp_lp(g, ws)
+    torch.cuda.synchronize()
+    one = plan.bp_lp(g[0]).cpu().numpy()
+    assert np.array_equal(out[0].cpu().numpy(), one)
+    ref = obp.radon_bp_lp(og, g[37].cpu().numpy().astype(np.float64))
+    e = rel(out[37].cpu().numpy(), ref)
+    print(f"bp_lp 2048 slice 37 of 64: rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
