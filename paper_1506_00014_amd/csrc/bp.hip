@@ -13,6 +13,8 @@
 //   k_ramp          (shared) the FBP filter, before k_bp_rows_rfft
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "fft_device.h"
 #include "rl_internal.h"
 
@@ -25,6 +27,10 @@ namespace {
 constexpr int kBpPad = kPrefR + 2;
 constexpr int kGx = 16, kGy = 16;  // pixels per gather block (kGx * kGy == kThreads)
 static_assert(kGx * kGy == kThreads, "one pixel per thread");
+constexpr int kBch = 8;   // slices per gather thread: the FP64 geometry of a pixel is computed once for them
+constexpr int kBox = 1024;  // LDS floats of one slice's lattice box in the gather (16 x 16 pixels
+                            // need at most 780 at 2048^2, M = 4; larger boxes read global memory)
+constexpr int kFirRun = 8;  // consecutive prefilter outputs per thread (inputs held in registers)
 
 size_t bp_rows_lds(const DevPlan& d) {
   return (size_t)(d.n_rho + 2 * (d.n_s + 2 * kBpPad)) * sizeof(float);
@@ -58,14 +64,25 @@ __global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const floa
     gs[i] = (k >= 0 && k < ns) ? src[k] : 0.f;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nw; i += blockDim.x) {
-    float acc = P.pref[0] * gs[i];
-    for (int d = 1; d <= kPrefR; ++d) {
-      const float l = i - d >= 0 ? gs[i - d] : 0.f;
-      const float r = i + d < nw ? gs[i + d] : 0.f;
-      acc += P.pref[d] * (l + r);
+  // c_i = sum_{|d| <= kPrefR} pref_|d| g_{i+d}: a thread computes kFirRun consecutive outputs
+  // from one window of inputs in registers
+  float h[kPrefR + 1];
+#pragma unroll
+  for (int d = 0; d <= kPrefR; ++d) h[d] = P.pref[d];
+  for (int i0 = threadIdx.x * kFirRun; i0 < nw; i0 += blockDim.x * kFirRun) {
+    float win[kFirRun + 2 * kPrefR];
+#pragma unroll
+    for (int u = 0; u < kFirRun + 2 * kPrefR; ++u) {
+      const int i = i0 - kPrefR + u;
+      win[u] = (i >= 0 && i < nw) ? gs[i] : 0.f;
     }
-    cs[i] = acc;
+#pragma unroll
+    for (int r = 0; r < kFirRun; ++r) {
+      float acc = h[0] * win[r + kPrefR];
+#pragma unroll
+      for (int d = 1; d <= kPrefR; ++d) acc += h[d] * (win[r + kPrefR - d] + win[r + kPrefR + d]);
+      if (i0 + r < nw) cs[i0 + r] = acc;
+    }
   }
   __syncthreads();
   const double cth = P.own_cos[m * P.n_own + o];
@@ -97,20 +114,39 @@ __global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const floa
   rfft_post(sh, nc, P.tw, P.tw_len, [&](int k, float2 xv) { dst[k] = xv; });
 }
 
-// Block: 16 x 16 pixels of one slice.  lat holds the support rows [batch][m][n_sup][n_rho]
-// of the convolved lattice (spline coefficients); support row kHalo is a partition's first
-// owned row.
+// Block: 16 x 16 pixels (each wave an 8 x 8 sub-tile) of kBch slices.  lat holds the support
+// rows [batch][m][n_sup][n_rho] of the convolved lattice (spline coefficients); support row
+// kHalo is a partition's first owned row.  Per partition the block finds the lattice box its
+// pixels' taps cover; if it fits kBox floats, the box of each slice is staged in LDS with
+// coalesced loads and the 16 taps are read there, otherwise they are read from global memory.
 __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* __restrict__ lat,
-                                                        float* __restrict__ img) {
-  const int ix = blockIdx.x * kGx + (int)(threadIdx.x % kGx);
-  const int iy = blockIdx.y * kGy + (int)(threadIdx.x / kGx);
-  const int b = blockIdx.z;
-  if (ix >= P.n || iy >= P.n) return;
+                                                        float* __restrict__ img, int batch) {
+  __shared__ float box[kBch][kBox];
+  __shared__ int red[2][4];  // per partition parity: min/max row base, min/max column base
+  const int t = (int)threadIdx.x, wv = t >> 6, ln = t & 63;
+  const int ix = blockIdx.x * kGx + (ln & 7) + 8 * (wv & 1);
+  const int iy = blockIdx.y * kGy + (ln >> 3) + 8 * (wv >> 1);
+  const int b0 = blockIdx.z * kBch;
+  const int nb = min(kBch, batch - b0);
+  const bool in_img = ix < P.n && iy < P.n;
+  const bool act = in_img && in_unit_disc(ix, iy, P.n);
   const double x1 = -1.0 + ix * P.dx, x2 = -1.0 + iy * P.dx;
   const int nr = P.n_rho;
-  float acc = 0.f;
-  if (in_unit_disc(ix, iy, P.n)) {
-    for (int m = 0; m < P.m; ++m) {
+  const size_t slice = (size_t)P.m * P.n_sup * nr;  // lattice floats of one slice
+  float acc[kBch];
+#pragma unroll
+  for (int bb = 0; bb < kBch; ++bb) acc[bb] = 0.f;
+  for (int m = 0; m < P.m; ++m) {
+    int* rd = red[m & 1];  // the other parity was last read before the previous barriers
+    if (t == 0) {
+      rd[0] = INT_MAX;
+      rd[1] = INT_MIN;
+      rd[2] = INT_MAX;
+      rd[3] = INT_MIN;
+    }
+    int kt = 1, kr = 0;
+    float wt[4], wr[4];
+    if (act) {
       double sm, cm;
       sincospi((double)m / (double)P.m, &sm, &cm);
       // y = T_m x = a_R Rot(-m beta) x + (1 - a_R, 0) (eq. Tdef)
@@ -119,28 +155,76 @@ __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* 
       const double T = (atan2(y2, y1) - P.phi0[m]) / P.dtheta;
       const double R = (0.5 * log(y1 * y1 + y2 * y2) - P.rho0) / P.d_rho;
       const double ft = floor(T), fr = floor(R);
-      float wt[4], wr[4];
       bspline_w6((float)(T - ft), wt);
       bspline_w6((float)(R - fr), wr);
       // |x| < 1 puts T in [1, n_own + 2) and R in [-1, n_rho - 1] (T_m maps the unit disc
       // onto D); the clamps only guard the loads
-      const int kt = min(max((int)ft, 1), P.n_sup - 3);
-      const int kr = min(max((int)fr, -1), nr - 1);
-      const float* L = lat + ((size_t)(b * P.m + m) * P.n_sup + (kt - 1)) * nr;
+      kt = min(max((int)ft, 1), P.n_sup - 3);
+      kr = min(max((int)fr, -1), nr - 1);
+    }
+    __syncthreads();  // the reset of rd is visible; the previous partition's box reads are done
+    if (act) {
+      atomicMin(&rd[0], kt);
+      atomicMax(&rd[1], kt);
+      atomicMin(&rd[2], kr);
+      atomicMax(&rd[3], kr);
+    }
+    __syncthreads();
+    if (rd[0] > rd[1]) continue;  // no pixel of the tile in the disc (uniform)
+    const int r0 = rd[0] - 1, nrow = rd[1] - rd[0] + 4;
+    const int c0 = rd[2] - 1, ncol = rd[3] - rd[2] + 4;
+    const float* L0 = lat + (size_t)(b0 * P.m + m) * P.n_sup * nr;  // row 0 of partition m, slice b0
+    if (nrow * ncol <= kBox) {  // uniform
+      const int nbox = nrow * ncol;
+      for (int bb = 0; bb < nb; ++bb) {
+        const float* Ls = L0 + bb * slice;
+        for (int e = t; e < nbox; e += kThreads) {
+          const int r = e / ncol, c = e - r * ncol;
+          box[bb][e] = Ls[(size_t)(r0 + r) * nr + wrap1(c0 + c, nr)];
+        }
+      }
+      __syncthreads();
+      if (act) {
+        const int base = (kt - 1 - r0) * ncol + (kr - 1 - c0);
+#pragma unroll
+        for (int bb = 0; bb < kBch; ++bb) {
+          if (bb < nb) {
+            const float* B = box[bb] + base;
+            float v = 0.f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const float* Br = B + a * ncol;
+              v += wt[a] * (wr[0] * Br[0] + wr[1] * Br[1] + wr[2] * Br[2] + wr[3] * Br[3]);
+            }
+            acc[bb] += v;
+          }
+        }
+      }
+    } else if (act) {
+      const float* Lk = L0 + (size_t)(kt - 1) * nr;
       int col[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) col[c] = wrap1(kr - 1 + c, nr);
-      float v = 0.f;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const float* Lr = L + (size_t)a * nr;
-        v += wt[a] * (wr[0] * Lr[col[0]] + wr[1] * Lr[col[1]] + wr[2] * Lr[col[2]] + wr[3] * Lr[col[3]]);
+      for (int bb = 0; bb < kBch; ++bb) {
+        if (bb < nb) {
+          const float* L = Lk + bb * slice;
+          float v = 0.f;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const float* Lr = L + (size_t)a * nr;
+            v += wt[a] * (wr[0] * Lr[col[0]] + wr[1] * Lr[col[1]] + wr[2] * Lr[col[2]] + wr[3] * Lr[col[3]]);
+          }
+          acc[bb] += v;
+        }
       }
-      acc += v;
     }
-    acc *= (1.0f / 36.0f);
   }
-  img[((size_t)b * P.n + iy) * P.n + ix] = acc;
+  if (in_img) {
+#pragma unroll
+    for (int bb = 0; bb < kBch; ++bb)
+      if (bb < nb) img[((size_t)(b0 + bb) * P.n + iy) * P.n + ix] = acc[bb] * (1.0f / 36.0f);
+  }
 }
 
 rl_status prepare_bp_launches(const rl_plan* p) {
@@ -165,8 +249,8 @@ static rl_status bp_lp_chain(const rl_plan* plan, const float* sino, float* img,
   }
   if ((st = launch_theta_conv(plan, A, d.n_own, kHalo, Bs, d.n_sup, 0, false, batch, s, d.Hbp)) != RL_OK) return st;
   if ((st = launch_irfft_rows(plan, Bs, U, batch * d.m * d.n_sup, s)) != RL_OK) return st;
-  dim3 grid((d.n + kGx - 1) / kGx, (d.n + kGy - 1) / kGy, batch);
-  RL_LAUNCH("k_bp_gather", k_bp_gather, grid, dim3(kThreads), 0, s, d, U, img);
+  dim3 grid((d.n + kGx - 1) / kGx, (d.n + kGy - 1) / kGy, (batch + kBch - 1) / kBch);
+  RL_LAUNCH("k_bp_gather", k_bp_gather, grid, dim3(kThreads), 0, s, d, U, img, batch);
   return check_launch("k_bp_gather");
 }
 
