@@ -28,6 +28,7 @@ constexpr int kBpPad = kPrefR + 2;
 constexpr int kGx = 16, kGy = 16;  // pixels per gather block (kGx * kGy == kThreads)
 static_assert(kGx * kGy == kThreads, "one pixel per thread");
 constexpr int kBch = 8;   // slices per gather thread: the FP64 geometry of a pixel is computed once for them
+constexpr int kStageMin = 4;  // calls with at least this many slices stage lattice boxes in LDS
 constexpr int kBox = 1024;  // LDS floats of one slice's lattice box in the gather (16 x 16 pixels
                             // need at most 780 at 2048^2, M = 4; larger boxes read global memory)
 constexpr int kFirRun = 8;  // consecutive prefilter outputs per thread (inputs held in registers)
@@ -119,9 +120,12 @@ __global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const floa
 // kHalo is a partition's first owned row.  Per partition the block finds the lattice box its
 // pixels' taps cover; if it fits kBox floats, the box of each slice is staged in LDS with
 // coalesced loads and the 16 taps are read there, otherwise they are read from global memory.
+// STAGED = false reads every tap from global memory (no LDS, no barriers): calls with fewer
+// than kStageMin slices gain nothing from the staging and lose occupancy to its LDS.
+template <bool STAGED>
 __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* __restrict__ lat,
                                                         float* __restrict__ img, int batch) {
-  __shared__ float box[kBch][kBox];
+  __shared__ float box[STAGED ? kBch : 1][STAGED ? kBox : 1];
   __shared__ int red[2][4];  // per partition parity: min/max row base, min/max column base
   const int t = (int)threadIdx.x, wv = t >> 6, ln = t & 63;
   const int ix = blockIdx.x * kGx + (ln & 7) + 8 * (wv & 1);
@@ -138,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* 
   for (int bb = 0; bb < kBch; ++bb) acc[bb] = 0.f;
   for (int m = 0; m < P.m; ++m) {
     int* rd = red[m & 1];  // the other parity was last read before the previous barriers
-    if (t == 0) {
+    if (STAGED && t == 0) {
       rd[0] = INT_MAX;
       rd[1] = INT_MIN;
       rd[2] = INT_MAX;
@@ -162,19 +166,24 @@ __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* 
       kt = min(max((int)ft, 1), P.n_sup - 3);
       kr = min(max((int)fr, -1), nr - 1);
     }
-    __syncthreads();  // the reset of rd is visible; the previous partition's box reads are done
-    if (act) {
-      atomicMin(&rd[0], kt);
-      atomicMax(&rd[1], kt);
-      atomicMin(&rd[2], kr);
-      atomicMax(&rd[3], kr);
-    }
-    __syncthreads();
-    if (rd[0] > rd[1]) continue;  // no pixel of the tile in the disc (uniform)
-    const int r0 = rd[0] - 1, nrow = rd[1] - rd[0] + 4;
-    const int c0 = rd[2] - 1, ncol = rd[3] - rd[2] + 4;
     const float* L0 = lat + (size_t)(b0 * P.m + m) * P.n_sup * nr;  // row 0 of partition m, slice b0
-    if (nrow * ncol <= kBox) {  // uniform
+    int r0 = 0, nrow = 0, c0 = 0, ncol = 0;
+    if (STAGED) {
+      __syncthreads();  // the reset of rd is visible; the previous partition's box reads are done
+      if (act) {
+        atomicMin(&rd[0], kt);
+        atomicMax(&rd[1], kt);
+        atomicMin(&rd[2], kr);
+        atomicMax(&rd[3], kr);
+      }
+      __syncthreads();
+      if (rd[0] > rd[1]) continue;  // no pixel of the tile in the disc (uniform)
+      r0 = rd[0] - 1;
+      nrow = rd[1] - rd[0] + 4;
+      c0 = rd[2] - 1;
+      ncol = rd[3] - rd[2] + 4;
+    }
+    if (STAGED && nrow * ncol <= kBox) {  // uniform
       const int nbox = nrow * ncol;
       for (int bb = 0; bb < nb; ++bb) {
         const float* Ls = L0 + bb * slice;
@@ -250,7 +259,10 @@ static rl_status bp_lp_chain(const rl_plan* plan, const float* sino, float* img,
   if ((st = launch_theta_conv(plan, A, d.n_own, kHalo, Bs, d.n_sup, 0, false, batch, s, d.Hbp)) != RL_OK) return st;
   if ((st = launch_irfft_rows(plan, Bs, U, batch * d.m * d.n_sup, s)) != RL_OK) return st;
   dim3 grid((d.n + kGx - 1) / kGx, (d.n + kGy - 1) / kGy, (batch + kBch - 1) / kBch);
-  RL_LAUNCH("k_bp_gather", k_bp_gather, grid, dim3(kThreads), 0, s, d, U, img, batch);
+  if (batch >= kStageMin)
+    RL_LAUNCH("k_bp_gather", k_bp_gather<true>, grid, dim3(kThreads), 0, s, d, U, img, batch);
+  else
+    RL_LAUNCH("k_bp_gather", k_bp_gather<false>, grid, dim3(kThreads), 0, s, d, U, img, batch);
   return check_launch("k_bp_gather");
 }
 
