@@ -170,11 +170,20 @@ __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* 
     int r0 = 0, nrow = 0, c0 = 0, ncol = 0;
     if (STAGED) {
       __syncthreads();  // the reset of rd is visible; the previous partition's box reads are done
-      if (act) {
-        atomicMin(&rd[0], kt);
-        atomicMax(&rd[1], kt);
-        atomicMin(&rd[2], kr);
-        atomicMax(&rd[3], kr);
+      // reduce across the wave first (inactive lanes hold neutral values), one atomic per wave
+      int lo_t = act ? kt : INT_MAX, hi_t = act ? kt : INT_MIN, lo_r = act ? kr : INT_MAX, hi_r = act ? kr : INT_MIN;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        lo_t = min(lo_t, __shfl_xor(lo_t, off));
+        hi_t = max(hi_t, __shfl_xor(hi_t, off));
+        lo_r = min(lo_r, __shfl_xor(lo_r, off));
+        hi_r = max(hi_r, __shfl_xor(hi_r, off));
+      }
+      if (ln == 0 && lo_t <= hi_t) {
+        atomicMin(&rd[0], lo_t);
+        atomicMax(&rd[1], hi_t);
+        atomicMin(&rd[2], lo_r);
+        atomicMax(&rd[3], hi_r);
       }
       __syncthreads();
       if (rd[0] > rd[1]) continue;  // no pixel of the tile in the disc (uniform)
