@@ -13,6 +13,7 @@
 //   k_ramp          (shared) the FBP filter, before k_bp_rows_rfft
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "fft_device.h"
@@ -33,8 +34,11 @@ constexpr int kBox = 1024;  // LDS floats of one slice's lattice box in the gath
                             // need at most 780 at 2048^2, M = 4; larger boxes read global memory)
 constexpr int kFirRun = 8;  // consecutive prefilter outputs per thread (inputs held in registers)
 
+// The sinogram row and the lattice row share one region (the first is dead once the
+// coefficients are built); the coefficients follow it.
 size_t bp_rows_lds(const DevPlan& d) {
-  return (size_t)(d.n_rho + 2 * (d.n_s + 2 * kBpPad)) * sizeof(float);
+  const int nw = d.n_s + 2 * kBpPad;
+  return (size_t)(std::max(d.n_rho, nw) + nw) * sizeof(float);
 }
 
 }  // namespace
@@ -57,8 +61,9 @@ __global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const floa
   const bool wrap = (jw >> 30) & 1;
   float* x = reinterpret_cast<float*>(sh);  // [n_rho] the lattice row, then its FFT
   const int nw = ns + 2 * kBpPad;
-  float* gs = x + nr;   // [nw] the sinogram row at index k + kBpPad, zeros outside
-  float* cs = gs + nw;  // [nw] its spline coefficients, same indexing
+  float* gs = x;                   // [nw] the sinogram row at index k + kBpPad, zeros outside
+                                   // (dead once cs is built; x then takes its place)
+  float* cs = x + max(nr, nw);     // [nw] its spline coefficients, same indexing
   const float* src = sino + ((size_t)b * P.n_theta + j) * ns;
   for (int i = threadIdx.x; i < nw; i += blockDim.x) {
     const int k = i - kBpPad;
