@@ -33,12 +33,12 @@ def dev():
 _plans = {}
 
 
-def get_plan(n, nt, ns, m=4):
+def get_plan(n, nt, ns, m=4, **kw):
     from paper_1506_00014_amd import RadonPlan
 
-    key = (n, nt, ns, m)
+    key = (n, nt, ns, m, tuple(sorted(kw.items())))
     if key not in _plans:
-        p = RadonPlan(n, nt, ns, m=m)
+        p = RadonPlan(n, nt, ns, m=m, **kw)
         g = p.geom
         og = Geometry(g["n"], g["n_theta"], g["n_s"], g["m"], g["n_rho"], g["k_theta"], g["r_dec"]).validate()
         _plans[key] = (p, og)
@@ -73,6 +73,17 @@ def test_bp_lp_parity(dev, case):
     x = -1 + og.dx * np.arange(og.n)
     out = (x[None, :] ** 2 + x[:, None] ** 2) >= 1.0
     assert np.all(got[out] == 0.0)
+
+
+def test_bp_lp_oversampled_geometry(dev):
+    """N_rho and K above their defaults (finer lattice than the bounds ask for)."""
+    plan, og = get_plan(48, 64, 48, 4, n_rho=512, k_theta=64)
+    assert (og.n_rho, og.k_theta) == (512, 64)
+    g = inputs.normal_array((og.n_theta, og.n_s), 640)
+    got = plan.bp_lp(torch.tensor(g.astype(np.float32), device=dev)).cpu().numpy()
+    e = rel(got, obp.radon_bp_lp(og, f32(g)))
+    print(f"bp_lp oversampled (48, 64, 48, n_rho 512, K 64): rel L2 vs FP64 oracle {e:.2e}")
+    assert e <= TOL
 
 
 @pytest.mark.parametrize("case,batch", [((100, 150, 100, 3), 11), ((128, 180, 128, 4), 5), ((96, 97, 80, 5), 8)],
