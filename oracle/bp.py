@@ -52,9 +52,10 @@ Readings (where the paper is silent or garbled):
     method's discretisation error, not to rounding.
 
 Pins: tests/test_oracle_bp.py (zeta#_hat against the paper's closed form and its
-k_rho = 0 values; the interpolation property of the s-coefficients; closed-form
-back-projections of 1, s cos theta, s sin theta and s^2; agreement with the exact
-transpose on smooth data; FBP of a phantom).
+k_rho = 0 values; the interpolation property of the s-coefficients; the convolved
+lattice's spline through the plain zeta#_hat convolution at the nodes; closed-form
+back-projections of 1, s cos theta, s sin theta, s^2 and of a Gaussian's sinogram; FBP
+of a phantom; linearity).
 """
 
 from __future__ import annotations
