@@ -122,6 +122,14 @@ void rl_plan_destroy(rl_plan* plan);
 /* Copy the plan's geometry into *out. */
 rl_status rl_plan_geometry(const rl_plan* plan, rl_geom* out);
 
+/* Sinogram rows owned by each partition (sec. 2, eq. Radon_all_pb: row j belongs to partition
+ * m = [theta_j / beta mod M], rounding half up; the rows that round to M belong to partition 0
+ * with theta' = theta - pi and s -> -s).  Writes the largest count, n_own (the coarse rows of
+ * the log-polar lattice that carry data), to *n_own and, if rows is not NULL, the count of
+ * each of the M partitions to rows[0 .. M-1].  Host-side; RL_ERR_INVALID_ARG on a NULL plan
+ * or n_own. */
+rl_status rl_plan_rows(const rl_plan* plan, int32_t* n_own, int32_t* rows);
+
 /* Workspace bytes needed by one call of `op` on `batch` slices (0 if batch == 0). */
 size_t rl_workspace_bytes(const rl_plan* plan, int32_t batch, rl_op op);
 
@@ -150,6 +158,13 @@ rl_status radon_adj(const rl_plan* plan, const float* d_sino, float* d_img, int3
  * wrapper.  Same arguments, workspace (RL_OP_ADJ) and semantics as radon_adj. */
 rl_status radon_transpose(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch,
                           void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* (R#)^T f = (w_S / w_X) R f, the plain matrix transpose of radon_adj: the gradient map of
+ * radon_adj (for a loss L(R# g), dL/dg = (R#)^T dL/df), used by the autograd wrapper of R#.
+ * It runs the chain of radon_fwd with the factor w_S / w_X folded into its last step.  Same
+ * arguments, layouts, workspace (RL_OP_FWD) and errors as radon_fwd. */
+rl_status radon_adj_transpose(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch,
+                              void* d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* Filtered back-projection f = R# W g (sec. 1 eq. FBP): W is the filter of sec. 6 chosen by
  * `filter`, applied along s: the ramp |sigma| (eq. ramp) as a linear (zero-padded)

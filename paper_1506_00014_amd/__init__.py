@@ -6,6 +6,7 @@ does not load the library; the first plan does, and fails loudly if it is missin
 """
 
 __all__ = ["RadonPlan", "radon_fwd", "radon_adj", "radon_transpose", "fbp", "radon_bp_lp", "fbp_lp", "RadonFn", "radon",
+           "RadonAdjFn", "back_project",
            "RaggedBatch"]
 
 

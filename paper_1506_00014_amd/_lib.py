@@ -35,11 +35,13 @@ EXPORTED = (
     "rl_plan_create",
     "rl_plan_destroy",
     "rl_plan_geometry",
+    "rl_plan_rows",
     "rl_workspace_bytes",
     "rl_plan_samples",
     "radon_fwd",
     "radon_adj",
     "radon_transpose",
+    "radon_adj_transpose",
     "fbp",
     "radon_bp_lp",
     "fbp_lp",
@@ -108,7 +110,9 @@ def load(path: str = LIB_PATH):
     lib.rl_workspace_bytes.restype = c_size_t
     lib.rl_plan_samples.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int64)]
     lib.rl_plan_samples.restype = c_int32
-    for name in ("radon_fwd", "radon_adj", "radon_transpose", "radon_bp_lp"):
+    lib.rl_plan_rows.argtypes = [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]
+    lib.rl_plan_rows.restype = c_int32
+    for name in ("radon_fwd", "radon_adj", "radon_transpose", "radon_adj_transpose", "radon_bp_lp"):
         f = getattr(lib, name)
         f.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]
         f.restype = c_int32

@@ -114,6 +114,12 @@ class RadonPlan:
         sino = self._check_in(sino, (g["n_theta"], g["n_s"]), "sino")
         return self._run("radon_transpose", sino, (g["n"], g["n"]), _lib.RL_OP_ADJ, ws)
 
+    def adjoint_transpose(self, img, ws=None):
+        """(R#)^T f = (w_S / w_X) R f: [..., n, n] -> [..., n_theta, n_s]."""
+        g = self.geom
+        img = self._check_in(img, (g["n"], g["n"]), "img")
+        return self._run("radon_adj_transpose", img, (g["n_theta"], g["n_s"]), _lib.RL_OP_FWD, ws)
+
     def fbp(self, sino, ws=None, filter="ramlak"):
         """R# W g, W the "ramlak", "cosine" or "shepp-logan" filter: [..., n_theta, n_s] -> [..., n, n]."""
         if filter not in _lib.FILTERS:
@@ -199,12 +205,15 @@ class RadonPlan:
         return out
 
     def n_own(self):
-        g = self.geom
-        counts = [0] * g["m"]
-        for j in range(g["n_theta"]):
-            mm = (2 * j * g["m"] + g["n_theta"]) // (2 * g["n_theta"])
-            counts[0 if mm == g["m"] else mm] += 1
-        return max(counts)
+        """Largest number of sinogram rows one partition owns (rl_plan_rows)."""
+        return self.rows_per_partition()[0]
+
+    def rows_per_partition(self):
+        """(n_own, [rows owned by each partition]) from the library (rl_plan_rows)."""
+        n_own = ctypes.c_int32()
+        rows = (ctypes.c_int32 * self.geom["m"])()
+        _lib.check("rl_plan_rows", self._lib.rl_plan_rows(self._ptr, ctypes.byref(n_own), rows))
+        return int(n_own.value), [int(x) for x in rows]
 
 
 # ---------------------------------------------------------------------- functional API
@@ -248,6 +257,25 @@ class RadonFn(torch.autograd.Function):
 def radon(img, plan):
     """Differentiable R f."""
     return RadonFn.apply(img, plan)
+
+
+class RadonAdjFn(torch.autograd.Function):
+    """f = R# g with the hand-written backward dL/dg = (R#)^T dL/df = (w_S / w_X) R dL/df (the
+    radon_adj_transpose kernels)."""
+
+    @staticmethod
+    def forward(ctx, sino, plan):
+        ctx.plan = plan
+        return plan.adjoint(sino)
+
+    @staticmethod
+    def backward(ctx, grad):
+        return ctx.plan.adjoint_transpose(grad.contiguous()), None
+
+
+def back_project(sino, plan):
+    """Differentiable R# g."""
+    return RadonAdjFn.apply(sino, plan)
 
 
 class RaggedBatch:

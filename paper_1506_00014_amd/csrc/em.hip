@@ -128,7 +128,7 @@ extern "C" rl_status rl_em(const rl_plan* plan, const float* d_sino, const float
   float* back = (float*)(w + L.back);
   const size_t cs = (size_t)batch * d.n_theta * d.n_s, ci = (size_t)batch * d.n * d.n;
   for (int it = 0; it < iters; ++it) {
-    if ((st = forward_chain(plan, d_img, rf, batch, w + L.chain, -1, nullptr, stream)) != RL_OK) return st;
+    if ((st = forward_chain(plan, d_img, rf, batch, w + L.chain, -1, nullptr, stream, 1.0)) != RL_OK) return st;
     hipLaunchKernelGGL(k_em_ratio, grid_for(cs), dim3(kEThreads), 0, stream, d_sino, rf, cs, d.n_s, d.ds);
     if ((st = check_launch("k_em_ratio")) != RL_OK) return st;
     if ((st = adjoint_chain(plan, rf, back, batch, w + L.chain, RL_OP_ADJ, false, stream)) != RL_OK) return st;

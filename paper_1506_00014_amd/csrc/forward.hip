@@ -656,7 +656,7 @@ rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int
 // ------------------------------------------------------------------ inverse rho FFT + evaluation
 // Block: one owned row of one (slice, partition); writes sinogram row j.
 __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2* __restrict__ spec,
-                                                         float* __restrict__ sino) {
+                                                         float* __restrict__ sino, float scale) {
   extern __shared__ float2 sh[];
   const int o = blockIdx.x;
   const int bm = blockIdx.y;
@@ -670,7 +670,7 @@ __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2
   __syncthreads();
   fft_lds<kRowVals, true>(sh, nc, 1, P.twp_rows);
   const float* x = reinterpret_cast<const float*>(sh);
-  const float inv_aR = (float)(1.0 / (6.0 * P.a_R));  // 1/a_R and the weights' 1/6
+  const float inv_aR = (float)(scale / (6.0 * P.a_R));  // 1/a_R, the weights' 1/6, the output scale
   float* dst = sino + ((size_t)b * P.n_theta + j) * P.n_s;
   const int2* tr = P.tau + ((size_t)m * P.n_own + o) * P.n_s;  // rho position of each sample
   for (int k = threadIdx.x; k < P.n_s; k += blockDim.x) {
@@ -685,10 +685,12 @@ __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2
   }
 }
 
-rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, float* sino, int batch, hipStream_t s) {
+rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, float* sino, int batch, double scale,
+                            hipStream_t s) {
   const DevPlan& d = p->d;
   dim3 grid(d.n_own, batch * d.m);
-  RL_LAUNCH("k_irfft_eval", k_irfft_eval, grid, dim3(kThreads), d.nc * sizeof(float2), s, d, spec, sino);
+  RL_LAUNCH("k_irfft_eval", k_irfft_eval, grid, dim3(kThreads), d.nc * sizeof(float2), s, d, spec, sino,
+            (float)scale);
   return check_launch("k_irfft_eval");
 }
 
@@ -725,7 +727,7 @@ rl_status common_checks(const rl_plan* plan, const void* in, const void* out, in
 namespace rl {
 
 rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int batch, void* ws, int stop_stage,
-                        float* stage_out, hipStream_t s) {
+                        float* stage_out, hipStream_t s, double out_scale) {
   const DevPlan& d = plan->d;
   const WsLayout L = workspace_layout(plan, batch, RL_OP_FWD);
   char* w = (char*)ws;
@@ -742,13 +744,15 @@ rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int 
   if ((st = launch_rfft_rows(plan, u, A, batch * d.m * d.n_sup, s)) != RL_OK) return st;
   if ((st = launch_theta_conv(plan, A, d.n_sup, 0, Bs, d.n_own, kHalo, false, batch, s)) != RL_OK) return st;
   if (stop_stage == RL_STAGE_CONV) return launch_irfft_rows(plan, Bs, stage_out, batch * d.m * d.n_own, s);
-  return launch_irfft_eval(plan, Bs, sino, batch, s);
+  return launch_irfft_eval(plan, Bs, sino, batch, out_scale, s);
 }
 
 }  // namespace rl
 
-extern "C" rl_status radon_fwd(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch, void* d_ws,
-                               size_t ws_bytes, hipStream_t stream) {
+namespace {
+
+rl_status fwd_entry(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch, void* d_ws,
+                    size_t ws_bytes, hipStream_t stream, double out_scale) {
   rl_status st = RL_OK;
   if (plan) {
     const size_t ib = (size_t)batch * plan->d.n * plan->d.n * sizeof(float);
@@ -758,7 +762,21 @@ extern "C" rl_status radon_fwd(const rl_plan* plan, const float* d_img, float* d
     st = fail(RL_ERR_INVALID_ARG, "plan is NULL");
   }
   if (st != RL_OK || batch == 0) return st;
-  return forward_chain(plan, d_img, d_sino, batch, d_ws, -1, nullptr, stream);
+  return forward_chain(plan, d_img, d_sino, batch, d_ws, -1, nullptr, stream, out_scale);
+}
+
+}  // namespace
+
+extern "C" rl_status radon_fwd(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch, void* d_ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  return fwd_entry(plan, d_img, d_sino, batch, d_ws, ws_bytes, stream, 1.0);
+}
+
+extern "C" rl_status radon_adj_transpose(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch,
+                                         void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  if (!plan) return fail(RL_ERR_INVALID_ARG, "plan is NULL");
+  const DevPlan& d = plan->d;
+  return fwd_entry(plan, d_img, d_sino, batch, d_ws, ws_bytes, stream, (d.dtheta * d.ds) / (d.dx * d.dx));
 }
 
 extern "C" rl_status rl_debug_stage(const rl_plan* plan, rl_stage stage, const float* d_img, float* d_out,
@@ -782,5 +800,5 @@ extern "C" rl_status rl_debug_stage(const rl_plan* plan, rl_stage stage, const f
   const size_t ib = (size_t)d.n * d.n * sizeof(float);
   st = common_checks(plan, d_img, d_out, 1, d_ws, ws_bytes, RL_OP_FWD, ib, need);
   if (st != RL_OK) return st;
-  return forward_chain(plan, d_img, nullptr, 1, d_ws, (int)stage, d_out, stream);
+  return forward_chain(plan, d_img, nullptr, 1, d_ws, (int)stage, d_out, stream, 1.0);
 }

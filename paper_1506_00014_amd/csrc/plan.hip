@@ -703,6 +703,14 @@ extern "C" rl_status rl_plan_samples(const rl_plan* plan, int64_t* out) {
   return RL_OK;
 }
 
+extern "C" rl_status rl_plan_rows(const rl_plan* plan, int32_t* n_own, int32_t* rows) {
+  if (!plan || !n_own) return fail(RL_ERR_INVALID_ARG, "NULL argument");
+  *n_own = plan->d.n_own;
+  if (rows)
+    for (int p = 0; p < plan->d.m; ++p) rows[p] = plan->rows_per_part[p];
+  return RL_OK;
+}
+
 extern "C" rl_status rl_plan_geometry(const rl_plan* plan, rl_geom* out) {
   if (!plan || !out) return fail(RL_ERR_INVALID_ARG, "NULL argument");
   *out = plan->g;

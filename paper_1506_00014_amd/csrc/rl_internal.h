@@ -109,7 +109,8 @@ rl_status launch_rfft_rows(const rl_plan* p, const float* in, float2* out, int r
 rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out,
                             int out_rows, int out_off, bool conj, int batch, hipStream_t s,
                             const float2* H = nullptr);
-rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, float* sino, int batch,
+// scale: factor on the output (1 for R)
+rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, float* sino, int batch, double scale,
                             hipStream_t s);
 rl_status launch_splat_rfft(const rl_plan* p, const float* sino, float2* spec, int batch,
                             hipStream_t s);
@@ -130,7 +131,7 @@ std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small);
 // The operator chains behind radon_fwd and radon_adj / radon_transpose / fbp (arguments
 // checked by the caller; ws holds workspace_layout(plan, batch, RL_OP_FWD or op)).
 rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int batch, void* ws, int stop_stage,
-                        float* stage_out, hipStream_t s);
+                        float* stage_out, hipStream_t s, double out_scale);
 rl_status adjoint_chain(const rl_plan* plan, const float* sino, float* img, int batch, void* ws, rl_op op,
                         bool transpose, hipStream_t s);
 // Argument checks shared by the sinogram -> image entry points (op selects the workspace).

@@ -26,6 +26,20 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def max_rel(a, b):
+    """Largest elementwise error, relative to the largest reference value."""
+    a = np.asarray(a, np.float64)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def check(label, got, ref, tol=TOL):
+    """Relative L2 error (the bar) with the largest elementwise error beside it."""
+    e, mx = rel(got, ref), max_rel(got, ref)
+    print(f"{label}: rel L2 vs FP64 oracle {e:.2e}, max|d|/max|ref| {mx:.2e}")
+    assert e <= tol, label
+    return e
+
+
 @pytest.fixture(scope="module")
 def dev():
     if not torch.cuda.is_available():
@@ -68,6 +82,7 @@ CASES = [
 
 # larger theta-FFT lengths (K = 512, 1024, 2048) and the 1024 x 1024 configuration
 BIG_CASES = [
+    (768, 768, 768, 4, {}),   # the odd size of the ragged-batch mix (N_rho 2048, K 512)
     (256, 1024, 256, 4, {}),
     (512, 2048, 512, 4, {}),
     (256, 4096, 256, 4, {}),
@@ -88,15 +103,11 @@ def test_more_partitions_parity(dev, case):
     img, _ = inputs.ellipse_phantom(n, 8, 103)
     got = plan.forward(to_dev(img, dev)).cpu().numpy()
     ref = oradon.radon_fwd(og, f32(img))
-    e = rel(got, ref)
-    print(f"R M={m}: rel L2 vs FP64 oracle {e:.2e}")
-    assert e <= TOL
+    check(f"R M={m}", got, ref)
     g = inputs.normal_array((og.n_theta, og.n_s), 104)
     got = plan.adjoint(to_dev(g, dev)).cpu().numpy()
     ref = oradon.radon_adj(og, f32(g))
-    e = rel(got, ref)
-    print(f"R# M={m}: rel L2 vs FP64 oracle {e:.2e}")
-    assert e <= TOL
+    check(f"R# M={m}", got, ref)
 
 
 @pytest.mark.parametrize("case", BIG_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
@@ -106,15 +117,11 @@ def test_forward_adjoint_parity_large(dev, case):
     img, blobs_e, blobs_g = inputs.mixed_phantom(n, 30, 5, 201)
     got = plan.forward(to_dev(img, dev)).cpu().numpy()
     ref = oradon.radon_fwd(og, f32(img))
-    e = rel(got, ref)
-    print(f"R {case} K={og.k_theta}: rel L2 vs FP64 oracle {e:.2e}")
-    assert e <= TOL
+    check(f"R {case} K={og.k_theta}", got, ref)
     g = inputs.normal_array((nt, ns), 202)
     got = plan.adjoint(to_dev(g, dev)).cpu().numpy()
     ref = oradon.radon_adj(og, f32(g))
-    e = rel(got, ref)
-    print(f"R# {case} K={og.k_theta}: rel L2 vs FP64 oracle {e:.2e}")
-    assert e <= TOL
+    check(f"R# {case} K={og.k_theta}", got, ref)
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
@@ -125,9 +132,7 @@ def test_forward_parity(dev, case):
     img += 0.3 * inputs.uniform_image(n, 103)  # nonzero up to the image border
     got = plan.forward(to_dev(img, dev)).cpu().numpy()
     ref = oradon.radon_fwd(og, f32(img))
-    e = rel(got, ref)
-    print(f"R {case}: rel L2 vs FP64 oracle {e:.2e}")
-    assert e <= TOL
+    check(f"R {case}", got, ref)
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
@@ -137,13 +142,9 @@ def test_adjoint_parity(dev, case):
     g = inputs.normal_array((nt, ns), 102)
     got = plan.adjoint(to_dev(g, dev)).cpu().numpy()
     ref = oradon.radon_adj(og, f32(g))
-    e = rel(got, ref)
-    print(f"R# {case}: rel L2 vs FP64 oracle {e:.2e}")
-    assert e <= TOL
+    check(f"R# {case}", got, ref)
     gt = plan.transpose(to_dev(g, dev)).cpu().numpy()
-    et = rel(gt, ref * (og.w_X / og.w_S))
-    print(f"R^T {case}: rel L2 {et:.2e}")
-    assert et <= TOL
+    check(f"R^T {case}", gt, ref * (og.w_X / og.w_S))
 
 
 @pytest.mark.parametrize("case", CASES[:3], ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}")
@@ -156,9 +157,7 @@ def test_fbp_parity(dev, case):
     g = analytic.ellipse_sino(og.theta_nodes(), og.s_nodes(), ells)
     got = plan.fbp(to_dev(g, dev)).cpu().numpy()
     ref = oradon.fbp(og, f32(g))
-    e = rel(got, ref)
-    print(f"FBP {case}: rel L2 vs FP64 oracle {e:.2e}")
-    assert e <= TOL
+    check(f"FBP {case}", got, ref)
 
 
 @pytest.mark.parametrize("filt", ["cosine", "shepp-logan"])
@@ -172,9 +171,7 @@ def test_fbp_filter_parity(dev, case, filt):
     g = analytic.ellipse_sino(og.theta_nodes(), og.s_nodes(), ells)
     got = plan.fbp(to_dev(g, dev), filter=filt).cpu().numpy()
     ref = oradon.fbp(og, f32(g), name=filt)
-    e = rel(got, ref)
-    print(f"FBP {filt} {case}: rel L2 vs FP64 oracle {e:.2e}")
-    assert e <= TOL
+    check(f"FBP {filt} {case}", got, ref)
     # the window changes the result well above the tolerance
     assert rel(plan.fbp(to_dev(g, dev)).cpu().numpy(), ref) > 10 * TOL
 
@@ -277,9 +274,7 @@ def test_autograd_gradient_matches_oracle(dev):
     loss.backward()
     grad = f.grad.double().cpu().numpy()
     ref = 2.0 * (og.w_X / og.w_S) * oradon.radon_adj(og, oradon.radon_fwd(og, f32(f0)) - f32(g))
-    e = rel(grad, ref)
-    print(f"autograd gradient vs oracle 2 R^T (R f - g): {e:.2e}")
-    assert e <= TOL
+    check("autograd gradient vs oracle 2 R^T (R f - g)", grad, ref)
 
 
 def test_errors_on_device(dev):
@@ -312,3 +307,50 @@ def test_fine_sample_count(dev, case):
     plan, og = get_plan(n, nt, ns, m, **kw)
     ref = sum(oradon.fine_sample_points(og, p)[0].size for p in range(og.m))
     assert plan.fine_samples() == ref
+
+
+def test_adjoint_autograd_gradient_matches_oracle(dev):
+    """RadonAdjFn: f = R# g with backward (R#)^T = (w_S / w_X) R.  For L(g) = ||R# g - b||^2 the
+    gradient is 2 (w_S / w_X) R (R# g - b); checked against the oracle at 128^2 and against
+    central differences (L is exactly quadratic, so any step gives the directional derivative)."""
+    from paper_1506_00014_amd import RadonAdjFn
+
+    n, nt, ns = 128, 180, 128
+    plan, og = get_plan(n, nt, ns)
+    g0 = inputs.normal_array((nt, ns), 341)
+    b, _ = inputs.ellipse_phantom(n, 8, 342)
+    y = to_dev(g0, dev).requires_grad_(True)
+    tb = to_dev(b, dev)
+    loss = ((RadonAdjFn.apply(y, plan) - tb) ** 2).sum()
+    loss.backward()
+    grad = y.grad.double().cpu().numpy()
+    ref = 2.0 * (og.w_S / og.w_X) * oradon.radon_fwd(og, oradon.radon_adj(og, f32(g0)) - f32(b))
+    check("RadonAdjFn gradient vs oracle 2 (w_S/w_X) R (R# g - b)", grad, ref)
+    # the backward entry point alone: (R#)^T f = (w_S / w_X) R f
+    x = inputs.normal_array((n, n), 343)
+    got = plan.adjoint_transpose(to_dev(x, dev)).cpu().numpy()
+    check("(R#)^T vs oracle (w_S/w_X) R", got, (og.w_S / og.w_X) * oradon.radon_fwd(og, f32(x)))
+    # central differences of the loss in 8 directions, in FP64 on the host
+    with torch.no_grad():
+        r0 = (plan.adjoint(to_dev(g0, dev)) - tb).double()
+        worst = 0.0
+        for k in range(8):
+            v = inputs.normal_array((nt, ns), 350 + k)
+            a = (plan.adjoint(to_dev(g0 + v, dev)) - tb).double()
+            bm = (plan.adjoint(to_dev(g0 - v, dev)) - tb).double()
+            fd = ((a - bm) * (a + bm)).sum().item() / 2.0
+            an = float(np.sum(grad * f32(v)))
+            worst = max(worst, abs(fd - an) / abs(an))
+    print(f"RadonAdjFn gradient vs central differences, 8 directions: worst relative error {worst:.2e}")
+    assert worst <= TOL
+    del r0
+
+
+def test_plan_rows_match_oracle(dev):
+    """rl_plan_rows: the rows each partition owns (eq. Radon_all_pb) as the oracle counts them."""
+    for case in CASES + BIG_CASES:
+        n, nt, ns, m, kw = case
+        plan, og = get_plan(n, nt, ns, m, **kw)
+        n_own, rows = plan.rows_per_partition()
+        assert rows == [len(og.partition_rows(p)) for p in range(og.m)], case
+        assert n_own == og.n_own, case
