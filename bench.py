@@ -3,10 +3,12 @@
 
 One step = the whole hot path on one batch of 2048 x 2048 slices (2048 angles x 2048 bins):
 g = R f, then R# g, then FBP g (ramp + R#).  Inputs are resident in HBM before the timed
-region.  Also reported: per-operator slices/s batched (one call for the batch) vs plain
-(batch-1 calls in a loop), per-kernel durations from HIP events recorded on the launch
-stream, the roofline position of the dominant kernel, and the FP64 oracle timed on the
-host on a bounded sample of the same workload.
+region.  Also reported: per-operator slices/s batched (the batch's kernels as one HIP graph
+replay, and eagerly) vs plain (batch-1 calls in a loop) with each operator's HBM fraction on
+algorithmic bytes and its roofline fraction max(t_HBM, t_VALU, t_LDS) / t, per-kernel durations
+from HIP events recorded on the launch stream, the roofline position of the dominant kernel,
+the 1024 x 1024 geometry's R, R# and FBP, the batched least-squares reconstruction by autograd,
+ragged batches, and the FP64 oracle timed on the host on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--no-cpu-baseline]
 """
@@ -32,6 +34,48 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 # the 4 x 4 tensor-product weights and their sum (4 + 16 products, 16 sums), the eight
 # cubic weights (2 x 10), and the four-tap decimation filter or its transpose (8).
 ALG_FLOPS_PER_SAMPLE = {"k_lp2cart_adj": 64, "k_cart2lp": 64}
+LDS_PEAK_GBS = 128 * 256 * 2.4  # assumed LDS bandwidth: 128 B per clock per CU, 256 CUs, 2.4 GHz
+
+
+def _partition_constants(m):
+    beta = math.pi / m
+    sh, ch = math.sin(beta / 2), math.cos(beta / 2)
+    return sh / (1 + sh), (ch - sh) / (1 + sh)
+
+
+def operator_model(g, n_own, samples, batch):
+    """Algorithmic work of one R (or R#, its mirror) per slice at the method's minimum sizes, so
+    that padding never inflates it: N_rho at its bound (sec. 3 eq. vrho) and K = 2 n_own.
+
+      bytes  4 N^2 (image) + 4 N_theta N_s (sinogram) + 32 M n_own (N_rho/2 + 1) (the half
+             spectra written and read between the rho and theta FFT passes, twice) + the kernel
+             table 8 (K/2 + 1)(N_rho/2 + 1) once per batch
+      flops  prefilter 8 per pixel (the recursive form: two first-order passes per axis);
+             60 per fine sample inside D (16-tap bicubic, its weights, the decimation);
+             real rho FFTs 2.5 N_rho log2 N_rho per row (M (n_own + 4) rows forward, M n_own
+             inverse); complex theta FFTs 5 K log2 K per column, forward and inverse, M (N_rho/2 + 1)
+             columns; the multiplier 6 per lattice point; the 4-tap evaluation 18 per sinogram sample
+      lds    16 taps x 4 bytes per fine sample
+    Returns per-slice (bytes, flops, lds_bytes) and the times they take at the peaks."""
+    n, nt, ns, m = g["n"], g["n_theta"], g["n_s"], g["m"]
+    a_R, a_r = _partition_constants(m)
+    nr = math.ceil(math.log(a_r) / math.log(1.0 - 2.0 * a_R / n))
+    K = 2 * n_own
+    cols = nr // 2 + 1
+    by = 4 * n * n + 4 * nt * ns + 32 * m * n_own * cols + 8 * (K // 2 + 1) * cols / batch
+    fl = (8 * n * n + 60 * samples + 2.5 * nr * math.log2(nr) * m * (2 * n_own + 4)
+          + 2 * 5 * K * math.log2(K) * m * cols + 6 * m * K * cols + 18 * nt * ns)
+    lds = 64 * samples
+    return {"alg_bytes_per_slice": round(by), "alg_flops_per_slice": round(fl), "lds_bytes_per_slice": lds,
+            "t_hbm_us": by / (HBM_PEAK_GBS * 1e3), "t_valu_us": fl / (FP32_PEAK_TFLOPS * 1e6),
+            "t_lds_us": lds / (LDS_PEAK_GBS * 1e3), "n_rho_min": nr, "k_min": K}
+
+
+def roofline_fractions(model, ms_per_slice):
+    """HBM fraction on algorithmic bytes and roofline fraction max(t_HBM, t_VALU, t_LDS) / t."""
+    t_us = ms_per_slice * 1e3
+    return {"hbm_frac": round(model["t_hbm_us"] / t_us, 4),
+            "roofline_frac": round(max(model["t_hbm_us"], model["t_valu_us"], model["t_lds_us"]) / t_us, 4)}
 
 
 def kernel_bytes(name, g, n_own, batch):
@@ -120,10 +164,10 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def cpu_baseline(g, seed=303, parts=3):
-    """The FP64 oracle on `parts` of the M partitions of one slice: R, R# and the FBP filter.
-
-    Per-slice time = prefilters + M x (mean partition forward + mean partition transpose) + ramp."""
+def _cpu_sample(g, seed=303, parts=1):
+    """One timed sample of the FP64 oracle on `parts` of the M partitions of one slice: the
+    prefilter, the partition forwards (with their polar evaluation), the ramp filter and the
+    partition transposes.  Returns the component times in seconds."""
     import numpy as np
 
     from oracle import bspline, radon as oradon
@@ -131,12 +175,8 @@ def cpu_baseline(g, seed=303, parts=3):
     from paper_1506_00014_amd import inputs
 
     og = Geometry(g["n"], g["n_theta"], g["n_s"], g["m"], g["n_rho"], g["k_theta"], g["r_dec"]).validate()
-    M = og.m
-    parts = min(parts, M)
     f = inputs.uniform_image(g["n"], seed)
-    t0 = time.perf_counter()
     oradon._H(og)  # plan-time kernel table, not part of the sample
-    t_plan = time.perf_counter() - t0
     t0 = time.perf_counter()
     c = bspline.prefilter_2d(f)
     t_q = time.perf_counter() - t0
@@ -149,27 +189,88 @@ def cpu_baseline(g, seed=303, parts=3):
             gpart[j] = bspline.eval_periodic_1d(clp[i], tau) / og.a_R
         t_fwd += time.perf_counter() - t0
     t0 = time.perf_counter()
-    w = oradon.ramp_filter(og, gpart)  # ramp_filter runs over every sinogram row
-    t_ramp = time.perf_counter() - t0
+    oradon.ramp_filter(og, gpart[: max(1, og.n_theta // 16)])  # 1/16 of the rows, scaled below
+    t_ramp = 16.0 * (time.perf_counter() - t0)
     for p in range(parts):
         t0 = time.perf_counter()
         oradon._partition_adjoint(og, gpart, p, "fft")
         t_adj += time.perf_counter() - t0
-    del w
-    fwd, adj = t_fwd / parts, t_adj / parts
-    # one step per slice: R (Q + M partitions), R# (M partitions + Q), FBP (ramp + M partitions + Q)
-    per_slice = (t_q + M * fwd) + (M * adj + t_q) + (t_ramp + M * adj + t_q)
-    sample = t_q + t_fwd + t_adj + t_ramp
+    return {"q": t_q, "fwd": t_fwd / parts, "adj": t_adj / parts, "ramp": t_ramp}
+
+
+def _cpu_sample_worker(args):
+    from threadpoolctl import threadpool_limits
+
+    g, seed = args
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        r = _cpu_sample(g, seed)
+        r["wall"] = time.perf_counter() - t0
+    return r
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, log, reps=3):
+    """The FP64 oracle on the host cores, single-threaded (median of `reps` samples) and on all
+    cores (one sample per core, run concurrently in worker processes, each single-threaded: the
+    slices of a batch are independent).  Per-slice time of one step = R (prefilter + M partition
+    forwards) + R# (M partition transposes + prefilter) + FBP (ramp + M transposes + prefilter)."""
+    import statistics
+    from concurrent.futures import ProcessPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
+    M = g["m"]
+
+    def per_slice(r):
+        return (r["q"] + M * r["fwd"]) + (M * r["adj"] + r["q"]) + (r["ramp"] + M * r["adj"] + r["q"])
+
+    samples = []
+    with threadpool_limits(limits=1):
+        for k in range(reps):
+            t0 = time.perf_counter()
+            r = _cpu_sample(g, 303)
+            r["wall"] = time.perf_counter() - t0
+            samples.append(r)
+            log(f"cpu sample {k}: {r}")
+    st = statistics.median(per_slice(r) for r in samples)
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    cores = max(1, min(cores, os.cpu_count() or 1, 16))
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=cores) as ex:
+        par = list(ex.map(_cpu_sample_worker, [(g, 303 + i) for i in range(cores)]))
+    wall = time.perf_counter() - t0
+    # all-core throughput: `cores` slices' worth of samples finished in `wall` seconds; scale the
+    # sample (one partition each way) to a whole step per slice
+    sample_work = statistics.median(r["wall"] for r in par)
+    per_slice_par = statistics.median(per_slice(r) for r in par)
+    all_core = cores / (per_slice_par * wall / sample_work)
     return {
-        "value": 1.0 / per_slice,
+        "value": round(1.0 / st, 5),
         "unit": "slices/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"partitions 0..{parts - 1} of {M} of one {g['n']}x{g['n']} slice ({g['n_theta']}x{g['n_s']} "
-                   f"sinogram): prefilter {t_q:.2f}s, partition forward {fwd:.2f}s and partition transpose "
-                   f"{adj:.2f}s each (mean), ramp {t_ramp:.2f}s; {sample:.1f}s of CPU work scaled to one step "
-                   f"per slice (R + R# + FBP = 3 prefilters + {M} forward + {2 * M} transposed partitions + ramp); "
-                   f"plan-time kernel table {t_plan:.1f}s excluded; numpy FP64, single thread"),
+        "all_core_value": round(all_core, 5),
+        "all_core_cores": cores,
+        "nproc": os.cpu_count(),
+        "cpu_model": _cpu_model(),
+        "sample": (f"one partition forward (with its polar evaluation) and one partition transpose of one "
+                   f"{g['n']}x{g['n']} slice ({g['n_theta']}x{g['n_s']} sinogram), the prefilter and the ramp "
+                   f"filter (timed on 1/16 of the rows), scaled to one step per slice (3 prefilters + {M} "
+                   f"forward + {2 * M} transposed partitions + ramp); numpy FP64; value: median of {reps} "
+                   f"single-thread samples ({st:.1f} s per slice); all_core_value: {cores} single-thread "
+                   f"samples run concurrently in worker processes ({wall:.1f} s wall); plan-time kernel "
+                   f"table excluded"),
     }
 
 
@@ -267,6 +368,86 @@ def ragged_detail(torch, log, count=256, seed=401):
     return out
 
 
+def graph_time(torch, fn, reps):
+    """Mean ms of one replay of a HIP graph capturing fn() (the batch's kernels, enqueued once)."""
+    fn()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(graph, stream=st):
+            fn()
+    torch.cuda.current_stream().wait_stream(st)
+    graph.replay()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        graph.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def c2_detail(torch, time_op, log, batch=64, n=1024, seed=201):
+    """One 1024 x 1024 geometry (1024 angles x 1024 bins): R, R# and FBP timed separately on a
+    batch (one graph replay each) and per slice (plain batch-1 calls)."""
+    from paper_1506_00014_amd import RadonPlan, _lib
+
+    plan = RadonPlan(n, n, n)
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    f = torch.rand(batch, n, n, device="cuda", generator=gen)
+    ws = torch.empty(max(plan.workspace_bytes(batch, op) for op in (0, 1, 2)), dtype=torch.uint8, device="cuda")
+    ws1 = torch.empty(max(plan.workspace_bytes(1, op) for op in (0, 1, 2)), dtype=torch.uint8, device="cuda")
+    g = plan.forward(f, ws)
+    model = operator_model(plan.geom, plan.n_own(), plan.fine_samples(), batch)
+    out = {"geometry": plan.geom, "batch": batch}
+    for name, fb, f1 in (("R", lambda: plan.forward(f, ws), lambda i: plan.forward(f[i], ws1)),
+                         ("R#", lambda: plan.adjoint(g, ws), lambda i: plan.adjoint(g[i], ws1)),
+                         ("FBP", lambda: plan.fbp(g, ws), lambda i: plan.fbp(g[i], ws1))):
+        tb = graph_time(torch, fb, 5)
+        tp = time_op(lambda: [f1(i) for i in range(batch)], 1)
+        rec = {"graph_slices_per_s": round(batch / (tb / 1000.0), 1),
+               "plain_slices_per_s": round(batch / (tp / 1000.0), 1)}
+        if name != "FBP":
+            rec.update(roofline_fractions(model, tb / batch))
+        out[name] = rec
+        log(f"1024^2 {name}: {rec}")
+    return out
+
+
+def c5_detail(torch, log, count=64, n=2048, n_theta=1024, n_s=2048, steps=50, photons=1e4):
+    """Batched least-squares reconstruction by autograd: `count` 30-ellipse phantoms of n x n, their
+    analytic line integrals at n_theta x n_s as log Poisson data (photons per ray), `steps`
+    gradient steps on ||R f - g||^2 from f = 0 with step 1 / (2 ||R^T R||) (20 power steps), and
+    the relative error to the phantoms next to FBP's."""
+    from paper_1506_00014_amd import RadonPlan, inputs, recon
+
+    plan = RadonPlan(n, n_theta, n_s)
+    t0 = time.perf_counter()
+    phantoms, data = inputs.noisy_ellipse_stack(count, n, n_theta, n_s, 30, photons, torch.device("cuda", 0))
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    lam = 2.0 * recon.power_iteration(plan, 20, seed=502)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f = recon.least_squares_gd(plan, data, steps, lam, callback=lambda k, l: losses.append(l))
+    torch.cuda.synchronize()
+    t_gd = time.perf_counter() - t0
+    pn = phantoms.norm()
+    err = ((f - phantoms).norm() / pn).item()
+    err_fbp = ((plan.fbp(data) - phantoms).norm() / pn).item()
+    out = {"slices": count, "n": n, "n_theta": n_theta, "n_s": n_s, "photons_per_ray": photons, "steps": steps,
+           "lambda": lam, "rel_error_gd": round(err, 4), "rel_error_fbp_ramlak": round(err_fbp, 4),
+           "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+           "ms_per_step": round(t_gd * 1000.0 / steps, 3),
+           "slice_steps_per_s": round(count * steps / t_gd, 1), "data_generation_s": round(t_data, 2)}
+    log(f"reconstruction: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +460,8 @@ def main():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch detail measurement")
     ap.add_argument("--no-m-sweep", action="store_true",
                     help="skip the R / R# rates at M = 3, 4, 6, 8 partitions")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 1024^2 R / R# / FBP timings")
+    ap.add_argument("--no-c5", action="store_true", help="skip the batched least-squares reconstruction")
     ap.add_argument("--no-em", action="store_true",
                     help="skip the EM step measurement (its normalisation is a batch-1 back-projection)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -399,10 +582,15 @@ def main():
         "R# (Alg. 2)": (lambda: plan.bp_lp(sino, ws), lambda i: plan.bp_lp(sino[i], ws1)),
         "FBP (Alg. 2)": (lambda: plan.fbp_lp(sino, ws), lambda i: plan.fbp_lp(sino[i], ws1)),
     }
-    detail = {"per_op": {}, "kernels": kernels}
+    model = operator_model(g, n_own, plan.fine_samples(), B)
+    detail = {"per_op": {}, "kernels": kernels, "model": model}
     for op, (batched, single) in ops.items():
-        tb = time_op(batched, reps)
-        rec = {"batched_slices_per_s": round(B / (tb / 1000.0), 1), "batched_ms_per_slice": round(tb / B, 4)}
+        tb = graph_time(torch, batched, reps)
+        te = time_op(batched, reps)
+        rec = {"batched_slices_per_s": round(B / (tb / 1000.0), 1), "batched_ms_per_slice": round(tb / B, 4),
+               "batched_eager_slices_per_s": round(B / (te / 1000.0), 1)}
+        if op in ("R", "R#"):
+            rec.update(roofline_fractions(model, tb / B))
         if single is not None and not args.no_plain:
             tp = time_op(lambda: [single(i) for i in range(B)], 1)
             rec["plain_slices_per_s"] = round(B / (tp / 1000.0), 1)
@@ -414,6 +602,10 @@ def main():
         em_detail(plan, f, sino, B, reps, time_op, detail, log)
     if not args.no_m_sweep:
         detail["m_sweep"] = m_sweep_detail(n, time_op, log)
+    if not args.no_c2:
+        detail["c2_1024"] = c2_detail(torch, time_op, log)
+    if not args.no_c5:
+        detail["reconstruction"] = c5_detail(torch, log)
     if not args.no_ragged:
         detail["ragged_batch"] = ragged_detail(torch, log)
     detail["paper_context"] = ("GTX 770, CUDA 7, FP32, M=3, N_theta=1.5N: EM 100 steps on 2048 slices of 2048^2 "
@@ -442,10 +634,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        from threadpoolctl import threadpool_limits
-
-        with threadpool_limits(limits=1):  # numpy's BLAS on one thread, as the sample states
-            out["cpu_baseline"] = cpu_baseline(g)
+        out["cpu_baseline"] = cpu_baseline(g, log)
     out["detail"] = detail
     print(json.dumps(out))
 

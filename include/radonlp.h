@@ -22,8 +22,8 @@
  *     tensors).  Inputs and outputs must not overlap.  Outputs are fully overwritten.
  *   - Every operation is enqueued asynchronously on the given stream; no call
  *     allocates device memory, synchronises the host, or reads device memory from
- *     the host, except rl_plan_create (which builds and uploads tables) and
- *     rl_plan_destroy.  The workspace is caller-provided and must be at least
+ *     the host, except rl_plan_create (which builds and uploads tables),
+ *     rl_plan_destroy, rl_plan_autotune and rl_batch_create.  The workspace is caller-provided and must be at least
  *     rl_workspace_bytes(plan, batch, op) bytes, 256-byte aligned; it may be reused
  *     by consecutive calls on the same stream but not by concurrent calls.
  *   - Errors never abort: each call returns an rl_status, and rl_last_error() returns
@@ -100,6 +100,47 @@ typedef struct {
 } rl_geom;
 
 typedef struct rl_plan rl_plan;
+
+/* Execution-only launch parameters of a plan.  None of them changes any result: every output
+ * value is computed by the same arithmetic in the same order whatever they are, so results are
+ * bitwise identical for every setting; they only change block shapes and schedules.
+ *   theta_cols       spectrum columns per block of the theta-convolution pass (1 .. 8, capped
+ *                    at 256 / the larger factor of k_theta; 0 = the largest allowed)
+ *   theta_xcd_order  1: blocks of the theta pass are ordered so that neighbouring column strips
+ *                    (which share cache lines) run on the same XCD (L2); 0: launch order
+ *   prefilter_rows   image rows per block of the B-spline prefilter, a multiple of 32 in
+ *                    [32, 4096]
+ *   fwd_patch_split  1: forward gather tiles whose image box fits the small LDS patch run with
+ *                    it (more blocks per CU), the others with the large one; 0: all large
+ * Defaults (rl_plan_create): 0, 1, 512, 1. */
+typedef struct {
+  int32_t theta_cols;
+  int32_t theta_xcd_order;
+  int32_t prefilter_rows;
+  int32_t fwd_patch_split;
+} rl_tune;
+
+/* Read / replace the plan's launch parameters.  rl_plan_set_tuning validates *tune
+ * (RL_ERR_INVALID_ARG if a field is out of range) and must not run concurrently with calls that
+ * use the plan. */
+rl_status rl_plan_get_tuning(const rl_plan* plan, rl_tune* out);
+rl_status rl_plan_set_tuning(rl_plan* plan, const rl_tune* tune);
+
+/* Workspace bytes rl_plan_autotune needs for `batch` slices. */
+size_t rl_tune_workspace_bytes(const rl_plan* plan, int32_t batch);
+
+/* Autotuner: time radon_fwd and radon_adj on `batch` slices of synthetic data (written into the
+ * workspace) for candidate values of each field of rl_tune in turn (coordinate descent, each
+ * candidate timed with HIP events over three runs after one warm-up, keeping the fastest), and
+ * set the best on the plan.  If cache_path is not NULL, the result is first looked up in that
+ * file and, when absent, appended to it: one JSON object per line with the key
+ * "<arch> rocm=<HIP version> n=.. n_theta=.. n_s=.. m=.. n_rho=.. k_theta=.. r_dec=.. dec_filter=..
+ * batch=..", the four fields and the measured R and R# times.  Synchronous on `stream` (it waits
+ * for its own work), not capturable; not concurrent with other calls using the plan.  Errors:
+ * RL_ERR_WORKSPACE if ws_bytes < rl_tune_workspace_bytes(plan, batch); RL_ERR_INVALID_ARG for a
+ * NULL plan or batch < 1; RL_ERR_INTERNAL if the cache file cannot be written. */
+rl_status rl_plan_autotune(rl_plan* plan, int32_t batch, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                           const char* cache_path);
 
 /* Fill *out with the default geometry for (n, n_theta, n_s, m): n_rho and k_theta are
  * the smallest powers of two meeting their bounds, r_dec the smallest integer meeting
@@ -270,10 +311,13 @@ rl_status rl_profile_record(int32_t i, const char** name, float* ms);
  * two calls enqueue kernels on `stream` only: no allocation, host synchronisation or host
  * read, so a caller may capture them in a HIP graph and replay it with new buffer contents.
  * The buffers stay owned by the caller and must stay valid while the batch is used; input
- * and output buffers must not overlap.  tune_cache is reserved for launch-parameter tuning
- * and must be NULL.  Errors: RL_ERR_INVALID_ARG for NULL lists, count < 0, a plan index out
- * of range, a plan built on another device or a non-NULL tune_cache; RL_ERR_WORKSPACE for a
- * workspace smaller than rl_batch_workspace_bytes(batch, op) or not 256-byte aligned. */
+ * and output buffers must not overlap.  tune_cache (optional, a file path): each plan's launch
+ * parameters for the number of slices that use it are taken from that autotuner cache, or
+ * found by rl_plan_autotune (with a temporary workspace) and appended to it; the result is set
+ * on the plan (see rl_plan_set_tuning; results do not change).  Errors: RL_ERR_INVALID_ARG for
+ * NULL lists, count < 0, a plan index out of range or a plan built on another device;
+ * RL_ERR_WORKSPACE for a workspace smaller than rl_batch_workspace_bytes(batch, op) or not
+ * 256-byte aligned; the autotuner's errors. */
 typedef struct rl_batch rl_batch;
 
 rl_status rl_batch_create(const rl_plan* const* plans, int32_t nplans, const int32_t* plan_of_slice,

@@ -36,6 +36,10 @@ EXPORTED = (
     "rl_plan_destroy",
     "rl_plan_geometry",
     "rl_plan_rows",
+    "rl_plan_get_tuning",
+    "rl_plan_set_tuning",
+    "rl_tune_workspace_bytes",
+    "rl_plan_autotune",
     "rl_workspace_bytes",
     "rl_plan_samples",
     "radon_fwd",
@@ -77,6 +81,18 @@ class RlGeom(ctypes.Structure):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
+class RlTune(ctypes.Structure):
+    _fields_ = [
+        ("theta_cols", ctypes.c_int32),
+        ("theta_xcd_order", ctypes.c_int32),
+        ("prefilter_rows", ctypes.c_int32),
+        ("fwd_patch_split", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 class RadonLibError(RuntimeError):
     def __init__(self, func, status, message):
         super().__init__(f"{func} failed with {STATUS_NAMES.get(status, status)}: {message}")
@@ -112,6 +128,14 @@ def load(path: str = LIB_PATH):
     lib.rl_plan_samples.restype = c_int32
     lib.rl_plan_rows.argtypes = [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]
     lib.rl_plan_rows.restype = c_int32
+    lib.rl_plan_get_tuning.argtypes = [c_void_p, ctypes.POINTER(RlTune)]
+    lib.rl_plan_get_tuning.restype = c_int32
+    lib.rl_plan_set_tuning.argtypes = [c_void_p, ctypes.POINTER(RlTune)]
+    lib.rl_plan_set_tuning.restype = c_int32
+    lib.rl_tune_workspace_bytes.argtypes = [c_void_p, c_int32]
+    lib.rl_tune_workspace_bytes.restype = c_size_t
+    lib.rl_plan_autotune.argtypes = [c_void_p, c_int32, c_void_p, c_size_t, c_void_p, ctypes.c_char_p]
+    lib.rl_plan_autotune.restype = c_int32
     for name in ("radon_fwd", "radon_adj", "radon_transpose", "radon_adj_transpose", "radon_bp_lp"):
         f = getattr(lib, name)
         f.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]

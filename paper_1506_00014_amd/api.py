@@ -204,6 +204,29 @@ class RadonPlan:
         _lib.check("rl_debug_stage", st)
         return out
 
+    @property
+    def tuning(self):
+        """The plan's execution-only launch parameters (rl_plan_get_tuning) as a dict."""
+        t = _lib.RlTune()
+        _lib.check("rl_plan_get_tuning", self._lib.rl_plan_get_tuning(self._ptr, ctypes.byref(t)))
+        return t.as_dict()
+
+    @tuning.setter
+    def tuning(self, values):
+        t = _lib.RlTune(**{**self.tuning, **values})
+        _lib.check("rl_plan_set_tuning", self._lib.rl_plan_set_tuning(self._ptr, ctypes.byref(t)))
+
+    def autotune(self, batch, cache=None):
+        """Choose the launch parameters for `batch` slices by timing (rl_plan_autotune); `cache` is
+        an optional JSON-lines file read first and appended to.  Returns the chosen parameters."""
+        need = int(self._lib.rl_tune_workspace_bytes(self._ptr, batch))
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            st = self._lib.rl_plan_autotune(self._ptr, int(batch), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(need),
+                                            _stream_ptr(self.device), None if cache is None else str(cache).encode())
+        _lib.check("rl_plan_autotune", st)
+        return self.tuning
+
     def n_own(self):
         """Largest number of sinogram rows one partition owns (rl_plan_rows)."""
         return self.rows_per_partition()[0]
@@ -286,9 +309,11 @@ class RaggedBatch:
     image (R), adjoint() every image from its sinogram (R#), each as one batched call per plan,
     enqueued on the current stream; neither allocates, so both can be captured in a CUDA (HIP)
     graph and replayed after the tensors' contents change.  The tensors must stay alive.
+    tune_cache: optional autotuner cache file; each plan's launch parameters for its slice count
+    come from it or are tuned and appended (rl_batch_create).
     """
 
-    def __init__(self, items):
+    def __init__(self, items, tune_cache=None):
         lib = _lib.load()
         plans, index = [], {}
         plan_of, imgs, sinos = [], [], []
@@ -314,7 +339,8 @@ class RaggedBatch:
         self._ptr = ctypes.c_void_p()
         self._lib = lib
         with torch.cuda.device(self.device):
-            _lib.check("rl_batch_create", lib.rl_batch_create(c_plans, len(plans), c_of, c_imgs, c_sinos, n, None,
+            cache = None if tune_cache is None else str(tune_cache).encode()
+            _lib.check("rl_batch_create", lib.rl_batch_create(c_plans, len(plans), c_of, c_imgs, c_sinos, n, cache,
                                                               ctypes.byref(self._ptr)))
             nbytes = max(int(lib.rl_batch_workspace_bytes(self._ptr, op)) for op in (0, 1))
             self._ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)

@@ -27,7 +27,7 @@ namespace rl {
 // an FP64 row in LDS (FP64 LDS atomics are fast on this target; where tau moves by more than
 // one rho step from sample to sample, as usual, the lanes of one add hit distinct entries).  The row is
 // then converted to FP32 in place and real-FFT'd.
-__global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float* __restrict__ sino,
+__global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, Slices<const float> sino,
                                                          float2* __restrict__ spec) {
   extern __shared__ double acc[];  // n_rho entries; reused as the FP32 FFT buffer
   const int nc = P.nc, nr = P.n_rho, ns = P.n_s;
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, const float*
   }
   const int j = jw & ((1 << 30) - 1);
   const float inv_aR = (float)(1.0 / (6.0 * P.a_R));  // 1/a_R and the weights' 1/6
-  const float* src = sino + ((size_t)b * P.n_theta + j) * ns;
+  const float* __restrict__ src = sino.at(b) + (size_t)j * ns;
   const int2* tr = P.tau + ((size_t)m * P.n_own + o) * ns;  // rho position of each sample
   for (int q = threadIdx.x; q < nr; q += blockDim.x) acc[q] = 0.0;
   __syncthreads();
@@ -82,7 +82,7 @@ rl_status prepare_adjoint_launches(const rl_plan* p) {
                         "hipFuncSetAttribute(k_splat_rfft)");
 }
 
-rl_status launch_splat_rfft(const rl_plan* p, const float* sino, float2* spec, int batch, hipStream_t s) {
+rl_status launch_splat_rfft(const rl_plan* p, Slices<const float> sino, float2* spec, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   const size_t lds = (size_t)d.n_rho * sizeof(double);
   dim3 grid(d.n_own, batch * d.m);
@@ -771,7 +771,7 @@ rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int b
 }
 
 
-rl_status adjoint_chain(const rl_plan* plan, const float* sino, float* img, int batch, void* ws, rl_op op,
+rl_status adjoint_chain(const rl_plan* plan, Slices<const float> sino, Slices<float> img, int batch, void* ws, rl_op op,
                         bool transpose, hipStream_t s) {
   const DevPlan& d = plan->d;
   const WsLayout L = workspace_layout(plan, batch, op);
@@ -786,7 +786,7 @@ rl_status adjoint_chain(const rl_plan* plan, const float* sino, float* img, int 
   if ((st = launch_irfft_scale(plan, Bs, U, batch, s)) != RL_OK) return st;
   if ((st = launch_lp2cart_adj(plan, U, cbar, batch, s)) != RL_OK) return st;
   const double scale = transpose ? 1.0 : (d.dtheta * d.ds) / (d.dx * d.dx);  // w_S / w_X for R#
-  return launch_prefilter(plan, cbar, img, batch, (float)scale, s);
+  return launch_prefilter(plan, dense((const float*)cbar, (size_t)d.n * d.n), img, batch, (float)scale, s);
 }
 
 }  // namespace rl
@@ -795,14 +795,18 @@ extern "C" rl_status radon_adj(const rl_plan* plan, const float* d_sino, float* 
                                size_t ws_bytes, hipStream_t stream) {
   rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_ADJ);
   if (st != RL_OK || batch == 0) return st;
-  return adjoint_chain(plan, d_sino, d_img, batch, d_ws, RL_OP_ADJ, false, stream);
+  const DevPlan& d = plan->d;
+  return adjoint_chain(plan, dense(d_sino, (size_t)d.n_theta * d.n_s), dense(d_img, (size_t)d.n * d.n), batch, d_ws,
+                       RL_OP_ADJ, false, stream);
 }
 
 extern "C" rl_status radon_transpose(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch,
                                      void* d_ws, size_t ws_bytes, hipStream_t stream) {
   rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_ADJ);
   if (st != RL_OK || batch == 0) return st;
-  return adjoint_chain(plan, d_sino, d_img, batch, d_ws, RL_OP_ADJ, true, stream);
+  const DevPlan& d = plan->d;
+  return adjoint_chain(plan, dense(d_sino, (size_t)d.n_theta * d.n_s), dense(d_img, (size_t)d.n * d.n), batch, d_ws,
+                       RL_OP_ADJ, true, stream);
 }
 
 extern "C" rl_status fbp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, rl_filter filter,
@@ -814,5 +818,7 @@ extern "C" rl_status fbp(const rl_plan* plan, const float* d_sino, float* d_img,
   const WsLayout L = workspace_layout(plan, batch, RL_OP_FBP);
   float* wg = (float*)((char*)d_ws + L.off[4]);
   if ((st = launch_ramp(plan, d_sino, wg, batch, (int)filter, stream)) != RL_OK) return st;
-  return adjoint_chain(plan, wg, d_img, batch, d_ws, RL_OP_FBP, false, stream);
+  const DevPlan& d = plan->d;
+  return adjoint_chain(plan, dense((const float*)wg, (size_t)d.n_theta * d.n_s), dense(d_img, (size_t)d.n * d.n), batch,
+                       d_ws, RL_OP_FBP, false, stream);
 }

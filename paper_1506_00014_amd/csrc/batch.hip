@@ -1,7 +1,7 @@
-// Ragged batches: slices of several geometries in one call per plan.  The slices of a plan
-// are gathered from their buffers into a contiguous block of the workspace, transformed by
-// one batched call, and the results scattered back.  Everything after rl_batch_create is a
-// kernel launch on the caller's stream (graph-capturable).
+// Ragged batches: slices of several geometries.  The slices of one plan run as one batched
+// call of its operator chain whose first and last kernels address each slice's own buffer
+// through a device table of pointers (built once by rl_batch_create), so no slice is copied.
+// Everything after rl_batch_create is kernel launches on the caller's stream (graph-capturable).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -9,52 +9,12 @@
 
 #include "rl_internal.h"
 
-namespace rl {
-namespace {
-
-// dst[s][i] = src[s][i] (gather: src through a pointer list) or dst[s][i] = src[s][i]
-// (scatter: dst through a pointer list), slice s = blockIdx.y.
-__global__ __launch_bounds__(kThreads) void k_gather(const float* const* __restrict__ src, float* __restrict__ dst,
-                                                     size_t elems, int vec4) {
-  const float* s = src[blockIdx.y];
-  float* d = dst + (size_t)blockIdx.y * elems;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (vec4) {
-    for (size_t i = t0; i < elems / 4; i += stride)
-      reinterpret_cast<float4*>(d)[i] = reinterpret_cast<const float4*>(s)[i];
-  } else {
-    for (size_t i = t0; i < elems; i += stride) d[i] = s[i];
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void k_scatter(const float* __restrict__ src, float* const* __restrict__ dst,
-                                                      size_t elems, int vec4) {
-  const float* s = src + (size_t)blockIdx.y * elems;
-  float* d = dst[blockIdx.y];
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (vec4) {
-    for (size_t i = t0; i < elems / 4; i += stride)
-      reinterpret_cast<float4*>(d)[i] = reinterpret_cast<const float4*>(s)[i];
-  } else {
-    for (size_t i = t0; i < elems; i += stride) d[i] = s[i];
-  }
-}
-
-size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-}  // namespace
-}  // namespace rl
-
 using namespace rl;
 
 struct rl_batch {
   struct Group {
     const rl_plan* plan;
     int first, count;    // slices [first, first + count) of the device pointer lists
-    size_t img_elems, sino_elems;
-    bool img_vec4, sino_vec4;  // all buffers 16-byte aligned and whole float4 rows
   };
   int device;
   int count;
@@ -64,44 +24,17 @@ struct rl_batch {
 
 namespace {
 
-size_t group_ws(const rl_batch::Group& g, rl_op op) {
-  const size_t io = al256(sizeof(float) * g.img_elems * g.count) + al256(sizeof(float) * g.sino_elems * g.count);
-  return io + rl_workspace_bytes(g.plan, g.count, op);
-}
+size_t group_ws(const rl_batch::Group& g, rl_op op) { return rl_workspace_bytes(g.plan, g.count, op); }
 
-// Gather the group's inputs, run `op` on them as one batch, scatter the outputs.
-rl_status run_group(const rl_batch* b, const rl_batch::Group& g, bool fwd, char* ws, size_t ws_bytes,
-                    hipStream_t s) {
-  float* imgs = reinterpret_cast<float*>(ws);
-  float* sinos = reinterpret_cast<float*>(ws + al256(sizeof(float) * g.img_elems * g.count));
-  char* rest = ws + al256(sizeof(float) * g.img_elems * g.count) + al256(sizeof(float) * g.sino_elems * g.count);
-  const size_t rest_bytes = ws_bytes - (size_t)(rest - ws);
-  float** img_ptrs = b->d_ptrs + g.first;
-  float** sino_ptrs = b->d_ptrs + b->count + g.first;
-  auto blocks = [](size_t elems) { return dim3((unsigned)std::min<size_t>((elems / 4 + kThreads - 1) / kThreads + 1, 1024)); };
-  rl_status st;
-  if (fwd) {
-    dim3 gi = blocks(g.img_elems);
-    gi.y = g.count;
-    RL_LAUNCH("k_gather", k_gather, gi, dim3(kThreads), 0, s, (const float* const*)img_ptrs, imgs, g.img_elems,
-              g.img_vec4 ? 1 : 0);
-    if ((st = check_launch("k_gather")) != RL_OK) return st;
-    if ((st = radon_fwd(g.plan, imgs, sinos, g.count, rest, rest_bytes, s)) != RL_OK) return st;
-    dim3 go = blocks(g.sino_elems);
-    go.y = g.count;
-    RL_LAUNCH("k_scatter", k_scatter, go, dim3(kThreads), 0, s, sinos, sino_ptrs, g.sino_elems, g.sino_vec4 ? 1 : 0);
-    return check_launch("k_scatter");
-  }
-  dim3 gi = blocks(g.sino_elems);
-  gi.y = g.count;
-  RL_LAUNCH("k_gather", k_gather, gi, dim3(kThreads), 0, s, (const float* const*)sino_ptrs, sinos, g.sino_elems,
-            g.sino_vec4 ? 1 : 0);
-  if ((st = check_launch("k_gather")) != RL_OK) return st;
-  if ((st = radon_adj(g.plan, sinos, imgs, g.count, rest, rest_bytes, s)) != RL_OK) return st;
-  dim3 go = blocks(g.img_elems);
-  go.y = g.count;
-  RL_LAUNCH("k_scatter", k_scatter, go, dim3(kThreads), 0, s, imgs, img_ptrs, g.img_elems, g.img_vec4 ? 1 : 0);
-  return check_launch("k_scatter");
+// Run `op` on the group's slices as one batch, reading and writing the slices in place.
+rl_status run_group(const rl_batch* b, const rl_batch::Group& g, bool fwd, void* ws, hipStream_t s) {
+  float* const* img_tab = b->d_ptrs + g.first;
+  float* const* sino_tab = b->d_ptrs + b->count + g.first;
+  if (fwd)
+    return forward_chain(g.plan, Slices<const float>{nullptr, img_tab, 0}, Slices<float>{nullptr, sino_tab, 0},
+                         g.count, ws, -1, nullptr, s, 1.0);
+  return adjoint_chain(g.plan, Slices<const float>{nullptr, sino_tab, 0}, Slices<float>{nullptr, img_tab, 0}, g.count,
+                       ws, RL_OP_ADJ, false, s);
 }
 
 rl_status batch_run(const rl_batch* b, bool fwd, void* d_ws, size_t ws_bytes, hipStream_t s) {
@@ -114,7 +47,7 @@ rl_status batch_run(const rl_batch* b, bool fwd, void* d_ws, size_t ws_bytes, hi
   if (!d_ws || ws_bytes < need) return fail(RL_ERR_WORKSPACE, "workspace smaller than rl_batch_workspace_bytes");
   if (((uintptr_t)d_ws & 255) != 0) return fail(RL_ERR_WORKSPACE, "workspace is not 256-byte aligned");
   for (const auto& g : b->groups) {
-    rl_status st = run_group(b, g, fwd, static_cast<char*>(d_ws), ws_bytes, s);
+    rl_status st = run_group(b, g, fwd, d_ws, s);
     if (st != RL_OK) return st;
   }
   return RL_OK;
@@ -127,7 +60,6 @@ extern "C" rl_status rl_batch_create(const rl_plan* const* plans, int32_t nplans
                                      const char* tune_cache, rl_batch** out) {
   if (!out) return fail(RL_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (tune_cache) return fail(RL_ERR_INVALID_ARG, "tune_cache is reserved and must be NULL");
   if (count < 0 || nplans < 0) return fail(RL_ERR_INVALID_ARG, "negative count");
   if (count > 0 && (!plans || !plan_of_slice || !d_imgs || !d_sinos))
     return fail(RL_ERR_INVALID_ARG, "NULL list");
@@ -150,21 +82,14 @@ extern "C" rl_status rl_batch_create(const rl_plan* const* plans, int32_t nplans
     g.plan = plans[p];
     g.first = k;
     g.count = 0;
-    g.img_vec4 = g.sino_vec4 = true;
     for (int i = 0; i < count; ++i) {
       if (plan_of_slice[i] != p) continue;
       ptrs[k] = d_imgs[i];
       ptrs[count + k] = d_sinos[i];
-      g.img_vec4 = g.img_vec4 && ((uintptr_t)d_imgs[i] & 15) == 0;
-      g.sino_vec4 = g.sino_vec4 && ((uintptr_t)d_sinos[i] & 15) == 0;
       ++k;
       ++g.count;
     }
     if (g.count == 0) continue;
-    g.img_elems = (size_t)g.plan->d.n * g.plan->d.n;
-    g.sino_elems = (size_t)g.plan->d.n_theta * g.plan->d.n_s;
-    g.img_vec4 = g.img_vec4 && g.img_elems % 4 == 0;
-    g.sino_vec4 = g.sino_vec4 && g.sino_elems % 4 == 0;
     b->groups.push_back(g);
   }
   if (count > 0) {
@@ -176,6 +101,23 @@ extern "C" rl_status rl_batch_create(const rl_plan* const* plans, int32_t nplans
       if (b->d_ptrs) (void)hipFree(b->d_ptrs);
       delete b;
       return st;
+    }
+  }
+  if (tune_cache) {
+    // launch parameters of each plan for its slice count: from the cache, else tuned now (with a
+    // temporary workspace, on the null stream) and appended to it
+    for (const auto& g : b->groups) {
+      rl_plan* p = const_cast<rl_plan*>(g.plan);  // only its execution-only launch parameters change
+      if (tune_from_cache(p, g.count, tune_cache)) continue;
+      const size_t need = rl_tune_workspace_bytes(p, g.count);
+      void* tmp = nullptr;
+      rl_status st = check_hip(hipMalloc(&tmp, need), "hipMalloc(autotune workspace)");
+      if (st == RL_OK) st = rl_plan_autotune(p, g.count, tmp, need, nullptr, tune_cache);
+      if (tmp) (void)hipFree(tmp);
+      if (st != RL_OK) {
+        rl_batch_destroy(b);
+        return st;
+      }
     }
   }
   *out = b;

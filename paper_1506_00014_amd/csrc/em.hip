@@ -103,7 +103,8 @@ extern "C" rl_status rl_em_norm(const rl_plan* plan, float* d_norm, void* d_ws, 
   const size_t cs = (size_t)d.n_theta * d.n_s;
   hipLaunchKernelGGL(k_em_chi, grid_for(cs), dim3(kEThreads), 0, stream, chi, cs, d.n_s, d.ds);
   if ((st = check_launch("k_em_chi")) != RL_OK) return st;
-  return adjoint_chain(plan, chi, d_norm, 1, (char*)d_ws + L.chain, RL_OP_ADJ, false, stream);
+  return adjoint_chain(plan, dense((const float*)chi, cs), dense(d_norm, (size_t)d.n * d.n), 1, (char*)d_ws + L.chain,
+                       RL_OP_ADJ, false, stream);
 }
 
 extern "C" rl_status rl_em(const rl_plan* plan, const float* d_sino, const float* d_norm, float* d_img, int32_t batch,
@@ -128,10 +129,14 @@ extern "C" rl_status rl_em(const rl_plan* plan, const float* d_sino, const float
   float* back = (float*)(w + L.back);
   const size_t cs = (size_t)batch * d.n_theta * d.n_s, ci = (size_t)batch * d.n * d.n;
   for (int it = 0; it < iters; ++it) {
-    if ((st = forward_chain(plan, d_img, rf, batch, w + L.chain, -1, nullptr, stream, 1.0)) != RL_OK) return st;
+    if ((st = forward_chain(plan, dense((const float*)d_img, (size_t)d.n * d.n), dense(rf, (size_t)d.n_theta * d.n_s),
+                            batch, w + L.chain, -1, nullptr, stream, 1.0)) != RL_OK)
+      return st;
     hipLaunchKernelGGL(k_em_ratio, grid_for(cs), dim3(kEThreads), 0, stream, d_sino, rf, cs, d.n_s, d.ds);
     if ((st = check_launch("k_em_ratio")) != RL_OK) return st;
-    if ((st = adjoint_chain(plan, rf, back, batch, w + L.chain, RL_OP_ADJ, false, stream)) != RL_OK) return st;
+    if ((st = adjoint_chain(plan, dense((const float*)rf, (size_t)d.n_theta * d.n_s), dense(back, (size_t)d.n * d.n),
+                            batch, w + L.chain, RL_OP_ADJ, false, stream)) != RL_OK)
+      return st;
     hipLaunchKernelGGL(k_em_update, grid_for(ci), dim3(kEThreads), 0, stream, d_img, back, d_norm, ci, d.n);
     if ((st = check_launch("k_em_update")) != RL_OK) return st;
   }

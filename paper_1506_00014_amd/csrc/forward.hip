@@ -21,29 +21,28 @@ namespace rl {
 constexpr int kPSW = 64;                   // output columns per block
 constexpr int kPSI = kPSW + 2 * kPrefR;    // input columns per block (96)
 constexpr int kPRB = 32;                   // rows per step
-constexpr int kPSeg = 512;                 // output rows per block
 constexpr int kPRing = kPRB + 2 * kPrefR;  // row-filtered rows kept (64, a power of two)
 constexpr int kPGroups = kPRB * kPSI / 4;  // float4 groups of input per step (768)
 static_assert(kPGroups % kThreads == 0, "whole groups per thread");
 static_assert(kPRB * (kPSW / 8) == kThreads && kPSW * (kPRB / 8) == kThreads,
               "one run of 8 outputs per thread in each filter pass");
 
-// Block: a strip of kPSW columns and up to kPSeg rows of one slice, streamed down in steps
+// Block: a strip of kPSW columns and up to `seg` rows of one slice, streamed down in steps
 // of kPRB rows.  A step row-filters kPRB new input rows (the periodic 2 kPrefR + 1 taps,
 // input staged in LDS) into a ring of the last kPRing row-filtered rows, then column-filters
 // the kPRB output rows whose taps the ring now holds.  The first step only fills the ring.
 // The next step's input is loaded into registers while the current step computes.
-__global__ __launch_bounds__(kThreads) void k_prefilter(const float* __restrict__ in, float* __restrict__ out,
-                                                        int n, float scale, const float* __restrict__ pref) {
+__global__ __launch_bounds__(kThreads) void k_prefilter(Slices<const float> in, Slices<float> out, int n, float scale,
+                                                        const float* __restrict__ pref, int seg) {
   __shared__ float tin[kPRB][kPSI + 1];
   __shared__ float ring[kPRing][kPSW + 1];
   __shared__ float q[kPrefR + 1];
   const int b = blockIdx.z;
   const int x0 = blockIdx.x * kPSW;
-  const int yseg0 = blockIdx.y * kPSeg, yseg1 = min(yseg0 + kPSeg, n);
+  const int yseg0 = blockIdx.y * seg, yseg1 = min(yseg0 + seg, n);
   const int base = yseg0 - kPrefR;  // row-filtered row y sits in ring slot (y - base) % kPRing
-  const float* src = in + (size_t)b * n * n;
-  float* dst = out + (size_t)b * n * n;
+  const float* __restrict__ src = in.at(b);
+  float* __restrict__ dst = out.at(b);
   if (threadIdx.x <= kPrefR) q[threadIdx.x] = pref[threadIdx.x];
   const bool vec_ok = (n & 3) == 0 && x0 - kPrefR >= 0 && x0 - kPrefR + kPSI <= n;  // uniform
   // input rows [ry, ry + kPRB) x columns [x0 - kPrefR, x0 - kPrefR + kPSI), periodic
@@ -128,10 +127,12 @@ __global__ __launch_bounds__(kThreads) void k_prefilter(const float* __restrict_
   }
 }
 
-rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int batch, float scale, hipStream_t s) {
+rl_status launch_prefilter(const rl_plan* p, Slices<const float> in, Slices<float> out, int batch, float scale,
+                           hipStream_t s) {
   const int n = p->d.n;
-  dim3 grid((n + kPSW - 1) / kPSW, (n + kPSeg - 1) / kPSeg, batch);
-  RL_LAUNCH("k_prefilter", k_prefilter, grid, dim3(kThreads), 0, s, in, out, n, scale, p->d.pref);
+  const int seg = p->tune.prefilter_rows;  // a multiple of kPRB
+  dim3 grid((n + kPSW - 1) / kPSW, (n + seg - 1) / seg, batch);
+  RL_LAUNCH("k_prefilter", k_prefilter, grid, dim3(kThreads), 0, s, in, out, n, scale, p->d.pref, seg);
   return check_launch("k_prefilter");
 }
 
@@ -409,14 +410,17 @@ rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, 
   const DevPlan& d = p->d;
   const int slot = prof_open("k_cart2lp", s);
   rl_status st = RL_OK;
-  if (d.ftiles_small > 0) {
-    hipLaunchKernelGGL(k_cart2lp<kFPatchSmall>, dim3(d.ftiles_small, batch), dim3(kFThreads),
+  // with the split off, every tile runs with the large patch (one launch over both lists)
+  const int n_small = p->tune.fwd_patch_split ? d.ftiles_small : 0;
+  const int n_large = d.ftiles_small + d.ftiles_large - n_small;
+  if (n_small > 0) {
+    hipLaunchKernelGGL(k_cart2lp<kFPatchSmall>, dim3(n_small, batch), dim3(kFThreads),
                        cart2lp_lds(d, kFPatchSmall), s, d, d.ftiles, c, u);
     st = check_launch("k_cart2lp");
   }
-  if (st == RL_OK && d.ftiles_large > 0) {
-    hipLaunchKernelGGL(k_cart2lp<kFPatch>, dim3(d.ftiles_large, batch), dim3(kFThreads), cart2lp_lds(d, kFPatch), s,
-                       d, d.ftiles + d.ftiles_small, c, u);
+  if (st == RL_OK && n_large > 0) {
+    hipLaunchKernelGGL(k_cart2lp<kFPatch>, dim3(n_large, batch), dim3(kFThreads), cart2lp_lds(d, kFPatch), s,
+                       d, d.ftiles + n_small, c, u);
     st = check_launch("k_cart2lp");
   }
   prof_close(slot, s);
@@ -489,7 +493,7 @@ rl_status launch_irfft_rows(const rl_plan* p, const float2* in, float* out, int 
 template <int K1, int K2>
 __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2* __restrict__ in, int in_rows,
                                                          int in_off, float2* __restrict__ out, int out_rows,
-                                                         int out_off, int conj, int cw) {
+                                                         int out_off, int conj, int cw, int xcd_order) {
   extern __shared__ float2 sh[];
   constexpr int K = K1 * K2;
   constexpr int RS = K2 + 1;           // padded stride between k1 rows
@@ -503,7 +507,8 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
     for (int i = threadIdx.x; i < K / 2; i += blockDim.x) dst4[i] = src4[i];
   }
   // neighbouring column strips share 128-byte lines: keep them on one XCD
-  const int lid = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  const int lid = xcd_order ? xcd_block(bid, gridDim.x * gridDim.y) : bid;
   const int bm = lid / gridDim.x;
   const int col0 = (lid - bm * gridDim.x) * cw;
   const float2* src = in + (size_t)bm * in_rows * P.ld;
@@ -586,19 +591,24 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
   }
 }
 
+// Columns per block of the theta pass: at most 256 / max(K1, K2) (one thread per column and row
+// of each stage), 8 at most (the default), or the plan's tuned value if it fits.
 template <int K1, int K2>
-static int theta_cw() {
-  return max(1, min(8, kThreads / max(K1, K2)));
+static int theta_cw(int tuned) {
+  const int cap = max(1, min(8, kThreads / max(K1, K2)));
+  return (tuned >= 1 && tuned <= cap) ? tuned : cap;
 }
 
 template <int K1, int K2>
-static size_t theta_lds() {
-  return ((size_t)theta_cw<K1, K2>() * (K1 * (K2 + 1) + 1) + 1 + K1 * K2) * sizeof(float2);
+static size_t theta_lds(int cw) {
+  return ((size_t)cw * (K1 * (K2 + 1) + 1) + 1 + K1 * K2) * sizeof(float2);
 }
 
 template <int K1, int K2>
 static rl_status theta_prepare() {
-  return ensure_dyn_lds((const void*)k_theta_conv<K1, K2>, theta_lds<K1, K2>(), "hipFuncSetAttribute(k_theta_conv)");
+  // the largest LDS any column count needs
+  return ensure_dyn_lds((const void*)k_theta_conv<K1, K2>, theta_lds<K1, K2>(theta_cw<K1, K2>(0)),
+                        "hipFuncSetAttribute(k_theta_conv)");
 }
 
 rl_status prepare_forward_launches(const rl_plan* p) {
@@ -627,13 +637,13 @@ static rl_status launch_theta_conv_t(const rl_plan* p, const float2* in, int in_
                                      const float2* H) {
   DevPlan d = p->d;
   if (H) d.H = H;
-  const int cw = theta_cw<K1, K2>();
-  const size_t lds = theta_lds<K1, K2>();
+  const int cw = theta_cw<K1, K2>(p->tune.theta_cols);
+  const size_t lds = theta_lds<K1, K2>(cw);
   rl_status st = ensure_dyn_lds((const void*)k_theta_conv<K1, K2>, lds, "hipFuncSetAttribute(k_theta_conv)");
   if (st != RL_OK) return st;
   dim3 grid((d.nc + 1 + cw - 1) / cw, batch * d.m);
   RL_LAUNCH("k_theta_conv", (k_theta_conv<K1, K2>), grid, dim3(kThreads), lds, s, d, in, in_rows, in_off, out,
-            out_rows, out_off, conj ? 1 : 0, cw);
+            out_rows, out_off, conj ? 1 : 0, cw, p->tune.theta_xcd_order);
   return check_launch("k_theta_conv");
 }
 
@@ -656,7 +666,7 @@ rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int
 // ------------------------------------------------------------------ inverse rho FFT + evaluation
 // Block: one owned row of one (slice, partition); writes sinogram row j.
 __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2* __restrict__ spec,
-                                                         float* __restrict__ sino, float scale) {
+                                                         Slices<float> sino, float scale) {
   extern __shared__ float2 sh[];
   const int o = blockIdx.x;
   const int bm = blockIdx.y;
@@ -671,7 +681,7 @@ __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2
   fft_lds<kRowVals, true>(sh, nc, 1, P.twp_rows);
   const float* x = reinterpret_cast<const float*>(sh);
   const float inv_aR = (float)(scale / (6.0 * P.a_R));  // 1/a_R, the weights' 1/6, the output scale
-  float* dst = sino + ((size_t)b * P.n_theta + j) * P.n_s;
+  float* __restrict__ dst = sino.at(b) + (size_t)j * P.n_s;
   const int2* tr = P.tau + ((size_t)m * P.n_own + o) * P.n_s;  // rho position of each sample
   for (int k = threadIdx.x; k < P.n_s; k += blockDim.x) {
     const int2 t = tr[k];
@@ -685,7 +695,7 @@ __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2
   }
 }
 
-rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, float* sino, int batch, double scale,
+rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, Slices<float> sino, int batch, double scale,
                             hipStream_t s) {
   const DevPlan& d = p->d;
   dim3 grid(d.n_own, batch * d.m);
@@ -726,8 +736,8 @@ rl_status common_checks(const rl_plan* plan, const void* in, const void* out, in
 
 namespace rl {
 
-rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int batch, void* ws, int stop_stage,
-                        float* stage_out, hipStream_t s, double out_scale) {
+rl_status forward_chain(const rl_plan* plan, Slices<const float> img, Slices<float> sino, int batch, void* ws,
+                        int stop_stage, float* stage_out, hipStream_t s, double out_scale) {
   const DevPlan& d = plan->d;
   const WsLayout L = workspace_layout(plan, batch, RL_OP_FWD);
   char* w = (char*)ws;
@@ -736,7 +746,9 @@ rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int 
   float2* A = (float2*)(w + L.off[2]);
   float2* Bs = (float2*)(w + L.off[3]);
   rl_status st;
-  if ((st = launch_prefilter(plan, img, stop_stage == RL_STAGE_PREFILTER ? stage_out : c, batch, 1.0f, s)) != RL_OK)
+  const size_t nn = (size_t)d.n * d.n;
+  if ((st = launch_prefilter(plan, img, dense(stop_stage == RL_STAGE_PREFILTER ? stage_out : c, nn), batch, 1.0f, s)) !=
+      RL_OK)
     return st;
   if (stop_stage == RL_STAGE_PREFILTER) return RL_OK;
   if ((st = launch_cart2lp(plan, c, stop_stage == RL_STAGE_LOGPOLAR ? stage_out : u, batch, s)) != RL_OK) return st;
@@ -762,7 +774,9 @@ rl_status fwd_entry(const rl_plan* plan, const float* d_img, float* d_sino, int3
     st = fail(RL_ERR_INVALID_ARG, "plan is NULL");
   }
   if (st != RL_OK || batch == 0) return st;
-  return forward_chain(plan, d_img, d_sino, batch, d_ws, -1, nullptr, stream, out_scale);
+  const DevPlan& d = plan->d;
+  return forward_chain(plan, dense(d_img, (size_t)d.n * d.n), dense(d_sino, (size_t)d.n_theta * d.n_s), batch, d_ws,
+                       -1, nullptr, stream, out_scale);
 }
 
 }  // namespace
@@ -800,5 +814,6 @@ extern "C" rl_status rl_debug_stage(const rl_plan* plan, rl_stage stage, const f
   const size_t ib = (size_t)d.n * d.n * sizeof(float);
   st = common_checks(plan, d_img, d_out, 1, d_ws, ws_bytes, RL_OP_FWD, ib, need);
   if (st != RL_OK) return st;
-  return forward_chain(plan, d_img, nullptr, 1, d_ws, (int)stage, d_out, stream, 1.0);
+  return forward_chain(plan, dense(d_img, ib / sizeof(float)), dense((float*)nullptr, 0), 1, d_ws, (int)stage, d_out,
+                       stream, 1.0);
 }

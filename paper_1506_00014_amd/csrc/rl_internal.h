@@ -20,6 +20,18 @@ constexpr int kTile = 64;         // image tile side of the adjoint splat
 constexpr int kPrefR = 16;        // half-length of the truncated prefilter (|z|^17 ~ 2e-10)
 constexpr int kMaxPart = 16;      // largest supported M
 
+// Slice b of a batch: base + b * stride, or tab[b] when a pointer table is given (the slices of
+// a ragged batch each live in a buffer of their own).  tab is a device array.
+template <class T>
+struct Slices {
+  T* base;
+  T* const* tab;
+  size_t stride;
+  __host__ __device__ T* at(int b) const { return tab ? tab[b] : base + (size_t)b * stride; }
+};
+template <class T>
+inline Slices<T> dense(T* base, size_t stride) { return Slices<T>{base, nullptr, stride}; }
+
 // Scalars and device tables handed to every kernel by value.
 struct DevPlan {
   int n, n_theta, n_s, m, n_rho, k_theta, r;
@@ -62,6 +74,7 @@ struct rl_plan {
   rl_geom g;
   int device;
   rl::DevPlan d;
+  rl_tune tune;  // execution-only launch parameters (rl_plan_set_tuning / rl_plan_autotune)
   std::vector<int> rows_per_part;
   void* d_mem;  // single device allocation holding all tables
   size_t d_mem_bytes;
@@ -101,7 +114,7 @@ void prof_close(int slot, hipStream_t s);
   } while (0)
 
 // Launchers (forward.hip / adjoint.hip).
-rl_status launch_prefilter(const rl_plan* p, const float* in, float* out, int batch, float scale,
+rl_status launch_prefilter(const rl_plan* p, Slices<const float> in, Slices<float> out, int batch, float scale,
                            hipStream_t s);
 rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s);
 rl_status launch_rfft_rows(const rl_plan* p, const float* in, float2* out, int rows, hipStream_t s);
@@ -110,9 +123,9 @@ rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int
                             int out_rows, int out_off, bool conj, int batch, hipStream_t s,
                             const float2* H = nullptr);
 // scale: factor on the output (1 for R)
-rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, float* sino, int batch, double scale,
+rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, Slices<float> sino, int batch, double scale,
                             hipStream_t s);
-rl_status launch_splat_rfft(const rl_plan* p, const float* sino, float2* spec, int batch,
+rl_status launch_splat_rfft(const rl_plan* p, Slices<const float> sino, float2* spec, int batch,
                             hipStream_t s);
 rl_status launch_irfft_scale(const rl_plan* p, const float2* spec, float* u, int batch,
                              hipStream_t s);
@@ -130,9 +143,9 @@ std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& 
 std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small);
 // The operator chains behind radon_fwd and radon_adj / radon_transpose / fbp (arguments
 // checked by the caller; ws holds workspace_layout(plan, batch, RL_OP_FWD or op)).
-rl_status forward_chain(const rl_plan* plan, const float* img, float* sino, int batch, void* ws, int stop_stage,
-                        float* stage_out, hipStream_t s, double out_scale);
-rl_status adjoint_chain(const rl_plan* plan, const float* sino, float* img, int batch, void* ws, rl_op op,
+rl_status forward_chain(const rl_plan* plan, Slices<const float> img, Slices<float> sino, int batch, void* ws,
+                        int stop_stage, float* stage_out, hipStream_t s, double out_scale);
+rl_status adjoint_chain(const rl_plan* plan, Slices<const float> sino, Slices<float> img, int batch, void* ws, rl_op op,
                         bool transpose, hipStream_t s);
 // Argument checks shared by the sinogram -> image entry points (op selects the workspace).
 rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int batch, void* ws, size_t ws_bytes,
@@ -141,6 +154,9 @@ rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int b
 rl_status prepare_bp_launches(const rl_plan* p);
 // Workspace of rl_em / rl_em_norm (em.hip).
 size_t em_workspace_bytes(const rl_plan* plan, int batch);
+// Set the plan's launch parameters from the autotuner cache at `path` (tune.hip): false if the
+// file has no entry for this plan and batch size.
+bool tune_from_cache(rl_plan* plan, int batch, const char* path);
 // Plan time: build the adjoint splat passes (allocates plan->d_adj, fills the adj_* fields).
 rl_status build_adj_passes(rl_plan* p);
 // Plan time: raise the LDS limits of the kernels this plan launches (see ensure_dyn_lds).

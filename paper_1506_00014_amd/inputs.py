@@ -85,3 +85,62 @@ def uniform_image(n, seed, lo=0.0, hi=1.0):
 
 def normal_array(shape, seed):
     return np.random.default_rng(seed).standard_normal(size=shape)
+
+
+# ---------------------------------------------------------------- noisy stacks (on the device)
+def rasterize_ellipses_torch(n, ellipses, device):
+    """rasterize_ellipses computed with torch on `device` (FP64), returned as float32."""
+    import torch
+
+    x = -1.0 + (2.0 / n) * torch.arange(n, dtype=torch.float64, device=device)
+    X2, X1 = torch.meshgrid(x, x, indexing="ij")  # row index = x2, column index = x1
+    img = torch.zeros(n, n, dtype=torch.float64, device=device)
+    for cx, cy, a, b, phi, rho0 in ellipses:
+        c, s = float(np.cos(phi)), float(np.sin(phi))
+        u = (X1 - cx) * c + (X2 - cy) * s
+        v = -(X1 - cx) * s + (X2 - cy) * c
+        img += rho0 * ((u / a) ** 2 + (v / b) ** 2 <= 1.0).double()
+    return img.float()
+
+
+def ellipse_line_integrals_torch(n_theta, n_s, ellipses, device):
+    """Exact line integrals of a sum of ellipse indicators (density rho0, centre c, semi-axes a
+    along angle phi and b) on the grid theta_j = j pi / n_theta, s_k = -1 + 2k / n_s, computed
+    with torch on `device` in FP64.  The line x . theta = s meets the ellipse in a chord of length
+    2 a b sqrt(w^2 - t^2) / w^2 where t = s - c . theta and w^2 = (a cos(theta - phi))^2 +
+    (b sin(theta - phi))^2 (the ellipse's half-width along theta).  Returned as float32."""
+    import torch
+
+    th = (np.pi / n_theta) * torch.arange(n_theta, dtype=torch.float64, device=device)[:, None]
+    s = -1.0 + (2.0 / n_s) * torch.arange(n_s, dtype=torch.float64, device=device)[None, :]
+    out = torch.zeros(n_theta, n_s, dtype=torch.float64, device=device)
+    for cx, cy, a, b, phi, rho0 in ellipses:
+        t = s - (cx * torch.cos(th) + cy * torch.sin(th))
+        w2 = (a * torch.cos(th - phi)) ** 2 + (b * torch.sin(th - phi)) ** 2
+        out += (2.0 * rho0 * a * b) * torch.sqrt(torch.clamp(w2 - t * t, min=0.0)) / w2
+    return out.float()
+
+
+def poisson_log_data(p, photons, seed):
+    """Log-transformed Poisson data: counts ~ Poisson(photons e^{-p}) (torch generator `seed` on
+    p's device), g = -log(max(counts, 1) / photons)."""
+    import torch
+
+    gen = torch.Generator(device=p.device)
+    gen.manual_seed(seed)
+    counts = torch.poisson(photons * torch.exp(-p.double()), generator=gen)
+    return (-torch.log(torch.clamp(counts, min=1.0) / photons)).float()
+
+
+def noisy_ellipse_stack(count, n, n_theta, n_s, n_ell, photons, device, seed0=5000, noise_seed=501):
+    """A stack of `count` ellipse phantoms (seeds seed0 + i, n_ell ellipses each) on `device`, with
+    their analytic line integrals turned into log Poisson data at `photons` incident photons per
+    ray: (phantoms [count][n][n], data [count][n_theta][n_s]), float32."""
+    import torch
+
+    imgs, ps = [], []
+    for i in range(count):
+        ells = draw_ellipses(np.random.default_rng(seed0 + i), n_ell)
+        imgs.append(rasterize_ellipses_torch(n, ells, device))
+        ps.append(ellipse_line_integrals_torch(n_theta, n_s, ells, device))
+    return torch.stack(imgs), poisson_log_data(torch.stack(ps), photons, noise_seed)

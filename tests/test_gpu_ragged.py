@@ -1,5 +1,7 @@
-"""Ragged batches (slices of several geometries, one call per plan) through the C-ABI:
-equality with per-slice calls, replay of a captured HIP graph, error codes."""
+"""Ragged batches (slices of several geometries, one call per plan, each slice read and written
+in its own buffer) through the C-ABI: equality with per-slice calls, replay of a captured HIP
+graph, error codes; the autotuner: results do not depend on the launch parameters, and its
+cache file is written once and read back."""
 
 import ctypes
 
@@ -102,7 +104,6 @@ def test_ragged_errors(setup):
     bad = (ctypes.c_int32 * 1)(1)  # plan index out of range
     assert lib.rl_batch_create(c_plans, 1, bad, c_imgs, c_sinos, 1, None, ctypes.byref(out)) == _lib.RL_ERR_INVALID_ARG
     ok = (ctypes.c_int32 * 1)(0)
-    assert lib.rl_batch_create(c_plans, 1, ok, c_imgs, c_sinos, 1, b"x", ctypes.byref(out)) == _lib.RL_ERR_INVALID_ARG
     assert lib.rl_batch_create(c_plans, 1, ok, c_imgs, c_sinos, 1, None, ctypes.byref(out)) == _lib.RL_OK
     need = lib.rl_batch_workspace_bytes(out, 0)
     assert need > 0
@@ -116,3 +117,56 @@ def test_ragged_errors(setup):
     assert lib.rl_batch_create(c_plans, 1, ok, c_imgs, c_sinos, 0, None, ctypes.byref(empty)) == _lib.RL_OK
     assert lib.rl_batch_fwd(empty, None, 0, stream) == _lib.RL_OK  # count 0: no-op
     lib.rl_batch_destroy(empty)
+
+
+def test_tuning_does_not_change_results(setup):
+    """Every value of every launch parameter gives the default's R bitwise and its R# to the FP64
+    accumulation order (the tile sums use LDS atomics)."""
+    dev, plans = setup
+    plan = plans[2]
+    n, nt, ns = GEOMS[2]
+    x = torch.tensor(inputs.ellipse_phantom(n, 8, 800)[0], dtype=torch.float32, device=dev).expand(3, n, n).contiguous()
+    y = torch.tensor(inputs.normal_array((3, nt, ns), 801), dtype=torch.float32, device=dev)
+    default = plan.tuning
+    r0, b0 = plan.forward(x), plan.adjoint(y)
+    try:
+        for field, values in (("theta_cols", (1, 2, 3, 8)), ("theta_xcd_order", (0,)), ("prefilter_rows", (32, 96, 1024)),
+                              ("fwd_patch_split", (0,))):
+            for v in values:
+                plan.tuning = {**default, field: v}
+                assert torch.equal(plan.forward(x), r0), (field, v)
+                e = ((plan.adjoint(y) - b0).abs().max() / b0.abs().max()).item()
+                assert e <= 1e-6, (field, v, e)
+        with pytest.raises(Exception):
+            plan.tuning = {**default, "prefilter_rows": 100}  # not a multiple of 32
+    finally:
+        plan.tuning = default
+
+
+def test_autotune_cache_and_ragged_batch(setup, tmp_path):
+    from paper_1506_00014_amd import RaggedBatch
+
+    dev, plans = setup
+    cache = tmp_path / "tune.jsonl"
+    defaults = [p.tuning for p in plans]
+    try:
+        items = make_items(dev, plans, 900)
+        batch = RaggedBatch(items, tune_cache=cache)
+        lines = cache.read_text().splitlines()
+        assert len(lines) == len(GEOMS)  # one entry per plan (each for its slice count)
+        for ln in lines:
+            assert '"key": "gfx950' in ln and "theta_cols" in ln
+        batch.forward()
+        torch.cuda.synchronize()
+        for plan, img, sino in items:
+            assert torch.equal(sino, plan.forward(img))
+        # a second batch of the same shapes reads the cache and tunes nothing
+        RaggedBatch(make_items(dev, plans, 950), tune_cache=cache)
+        assert cache.read_text().splitlines() == lines
+        # the plan-level call reads it too
+        tuned = plans[0].tuning
+        plans[0].tuning = defaults[0]
+        assert plans[0].autotune(PLAN_OF.count(0), cache=cache) == tuned
+    finally:
+        for p, d in zip(plans, defaults):
+            p.tuning = d
