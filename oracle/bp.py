@@ -196,6 +196,8 @@ def radon_bp_lp(geom, g) -> np.ndarray:
     """Algorithm 2: g[N_theta, N_s] -> f[N, N] (row = x2, column = x1)."""
     g = np.asarray(g, dtype=np.float64)
     assert g.shape == (geom.n_theta, geom.n_s)
+    if geom.q_theta != 1:
+        raise ValueError("Algorithm 2 here uses the lattice of the sinogram rows (q_theta = 1)")
     c = s_coefficients(g)                                            # P1
     H_full = multiplier_full(geom, multiplier_sharp_half(geom))
     f = np.zeros((geom.n, geom.n))

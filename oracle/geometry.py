@@ -21,10 +21,17 @@ shared, by the HIP path):
   * ownership uses round-half-up, computed exactly in integers; the rows the
     rounding assigns to m = M belong to partition 0 with theta' = theta - pi and
     s -> -s (each line appears twice in the parametrisation);
-  * each partition's coarse lattice has spacing Delta theta (the sinogram's),
-    its owned rows plus HALO rows on each side (the reach of the decimation
-    filter) form the support; the theta-FFT length is k_theta >= 2*ceil(N_theta/M);
-  * fine angular rows sit at Delta theta / r_dec, aligned with the coarse rows.
+  * each partition's coarse lattice has spacing Delta theta_c = Delta theta /
+    q_theta (q_theta = 1: the sinogram's), the lattice rows of its owned rows
+    plus HALO rows on each side (the reach of the decimation filter) form the
+    support; the theta-FFT length is k_theta >= 2*q_theta*ceil(N_theta/M);
+  * fine angular rows sit at Delta theta_c / r_dec, aligned with the coarse rows;
+  * accuracy variants (Algorithm 1 step 4 leaves the theta low-pass open; the
+    coarse grid Omega_p of eq. Lopolargrid_polar has the sinogram's spacing):
+    q_theta = 2 puts the coarse lattice at Delta theta_c = Delta theta / 2 (every
+    other lattice row lies on a sinogram row; the rows between are convolved
+    like the others but never evaluated), and dec_filter selects the low-pass
+    (kernel.decimation_taps).
 """
 
 from __future__ import annotations
@@ -43,10 +50,11 @@ def rho_bound(n: int, m: int) -> int:
     return int(math.ceil(math.log(a_r) / math.log(1.0 - 2.0 * a_R / n)))
 
 
-def r_bound(n: int, n_theta: int, m: int) -> int:
-    """Smallest fine oversampling r with Delta theta / r <= 2 a_R / N (sec. 3, before eq. Lopolargrid_f)."""
+def r_bound(n: int, n_theta: int, m: int, q_theta: int = 1) -> int:
+    """Smallest fine oversampling r with Delta theta_c / r <= 2 a_R / N (sec. 3, before
+    eq. Lopolargrid_f), Delta theta_c = Delta theta / q_theta the coarse lattice spacing."""
     a_R, _ = partition_constants(m)
-    return int(math.ceil((math.pi / n_theta) / (2.0 * a_R / n) - 1e-12))
+    return int(math.ceil((math.pi / (n_theta * q_theta)) / (2.0 * a_R / n) - 1e-12))
 
 
 def partition_constants(m: int):
@@ -75,6 +83,8 @@ class Geometry:
     n_rho: int
     k_theta: int
     r_dec: int
+    dec_filter: int = 0  # theta low-pass of step 4: 0 cubic B-spline, 1 box (kernel.decimation_taps)
+    q_theta: int = 1     # coarse lattice spacing Delta theta / q_theta (1 or 2)
 
     # ---------------------------------------------------------------- constants
     @property
@@ -109,6 +119,11 @@ class Geometry:
     @property
     def dtheta(self) -> float:
         return math.pi / self.n_theta
+
+    @property
+    def dtheta_c(self) -> float:
+        """Spacing of the coarse log-polar lattice Omega_p in theta'."""
+        return self.dtheta / self.q_theta
 
     @property
     def w_X(self) -> float:
@@ -160,23 +175,34 @@ class Geometry:
     def n_own(self) -> int:
         return max(len(self.partition_rows(p)) for p in range(self.m))
 
+    def n_lat(self, n_rows: int) -> int:
+        """Lattice rows spanned by n_rows consecutive owned sinogram rows."""
+        return self.q_theta * (n_rows - 1) + 1 if n_rows > 0 else 0
+
     @property
     def n_sup(self) -> int:
-        return self.n_own + 2 * HALO
+        return self.n_lat(self.n_own) + 2 * HALO
+
+    def n_sup_p(self, p: int) -> int:
+        """Support rows of partition p: the lattice rows of its owned rows plus HALO on each side."""
+        return self.n_lat(len(self.partition_rows(p))) + 2 * HALO
+
+    def lattice_row(self, pos: int) -> int:
+        """Lattice row of a partition's pos-th owned sinogram row."""
+        return HALO + self.q_theta * pos
 
     def phi0(self, p: int) -> float:
-        """Angle theta' of support row 0 of partition p (HALO rows below the first owned row)."""
+        """Angle theta' of support row 0 of partition p (HALO lattice rows below the first owned row)."""
         rows = self.partition_rows(p)
-        return math.pi * rows[0][2] / (self.n_theta * self.m) - HALO * self.dtheta
+        return math.pi * rows[0][2] / (self.n_theta * self.m) - HALO * self.dtheta_c
 
     def fine_rows(self, p: int) -> np.ndarray:
-        """Fine row indices t (phi_t = phi0 + t*dtheta/r) that feed partition p's support rows."""
+        """Fine row indices t (phi_t = phi0 + t*dtheta_c/r) that feed partition p's support rows."""
         r = self.r_dec
-        n_sup_p = len(self.partition_rows(p)) + 2 * HALO
-        return np.arange(-(2 * r - 1), r * (n_sup_p - 1) + 2 * r)
+        return np.arange(-(2 * r - 1), r * (self.n_sup_p(p) - 1) + 2 * r)
 
     def fine_phi(self, p: int, t) -> np.ndarray:
-        return self.phi0(p) + np.asarray(t, dtype=np.float64) * (self.dtheta / self.r_dec)
+        return self.phi0(p) + np.asarray(t, dtype=np.float64) * (self.dtheta_c / self.r_dec)
 
     def d_interval(self, phi):
         """Interval (e_lo, e_hi) of e^rho where the ray of angle phi meets D (eq. circle_D).
@@ -201,23 +227,29 @@ class Geometry:
             raise ValueError("need n_theta >= m and n_s >= 2")
         if self.n_rho < rho_bound(self.n, self.m):
             raise ValueError("n_rho below the sampling bound of eq. (vrho)")
-        if self.k_theta < 2 * math.ceil(self.n_theta / self.m) or self.k_theta < self.n_sup:
-            raise ValueError("k_theta must be >= 2*ceil(n_theta/m) and hold the support rows")
+        if self.q_theta not in (1, 2):
+            raise ValueError("q_theta must be 1 or 2")
+        if self.dec_filter not in (0, 1):
+            raise ValueError("dec_filter must be 0 (cubic B-spline) or 1 (box)")
+        if (self.k_theta < 2 * self.q_theta * math.ceil(self.n_theta / self.m)
+                or self.k_theta < self.n_sup):
+            raise ValueError("k_theta must be >= 2*q_theta*ceil(n_theta/m) and hold the support rows")
         if self.r_dec < 1:
             raise ValueError("r_dec must be >= 1")
         return self
 
 
-def make_geometry(n, n_theta, n_s, m=4, n_rho=None, k_theta=None, r_dec=None) -> Geometry:
+def make_geometry(n, n_theta, n_s, m=4, n_rho=None, k_theta=None, r_dec=None, dec_filter=0,
+                  q_theta=1) -> Geometry:
     """Geometry with the default choices: power-of-two FFT lengths at or above the
-    paper's bounds, K = 2*ceil(N_theta/M) rounded up, r at the fine-angle bound."""
+    paper's bounds, K = 2*q_theta*ceil(N_theta/M) rounded up, r at the fine-angle bound."""
     if n_rho is None:
         n_rho = _next_pow2(rho_bound(n, m))
     if k_theta is None:
-        k_theta = _next_pow2(2 * int(math.ceil(n_theta / m)))
+        k_theta = _next_pow2(2 * q_theta * int(math.ceil(n_theta / m)))
     if r_dec is None:
-        r_dec = r_bound(n, n_theta, m)
-    g = Geometry(n, n_theta, n_s, m, n_rho, k_theta, r_dec)
+        r_dec = r_bound(n, n_theta, m, q_theta)
+    g = Geometry(n, n_theta, n_s, m, n_rho, k_theta, r_dec, dec_filter, q_theta)
     if g.k_theta < g.n_sup:
-        g = Geometry(n, n_theta, n_s, m, n_rho, _next_pow2(g.n_sup), r_dec)
+        g = Geometry(n, n_theta, n_s, m, n_rho, _next_pow2(g.n_sup), r_dec, dec_filter, q_theta)
     return g.validate()

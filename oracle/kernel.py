@@ -9,7 +9,7 @@ Paper passages followed
         zeta_hat(k_theta, k_rho) = int_{-beta}^{beta} e^{-2 pi i k_theta u / P}
                                    (cos u)^{-2 pi i k_rho / L - 1} du ,
     with P the theta period of the FFT lattice (P = 2 beta for K = 2 N_theta/M,
-    exactly as printed; P = K * Delta theta in general) and L = -log a_r;
+    exactly as printed; P = K * Delta theta_c in general) and L = -log a_r;
   * the prefilter in rho folded into the multiplier (sec. 4, the remark that
     1/B_hat can be applied in the Fourier domain; Algorithm 1 step 6).
 
@@ -44,15 +44,25 @@ GL_NODES = 16
 PANEL_PHASE = 8.0  # max phase (radians) swept by the integrand inside one panel
 
 
-def decimation_taps(r: int) -> np.ndarray:
-    """d_n = B(n / r) / r for n = -(2r-1) .. 2r-1 (sum d_n = 1)."""
+def decimation_taps(r: int, kind: int = 0) -> np.ndarray:
+    """Taps d_n, n = -(2r-1) .. 2r-1, of the theta low-pass of Algorithm 1 step 4 (sum d_n = 1).
+
+    kind 0: the cubic B-spline d_n = B(n / r) / r.
+    kind 1: the box of one coarse cell centred on the coarse node, |phi - theta'_i| <= Delta
+            theta_c / 2, sampled by the trapezoid rule on the fine rows: 1/r inside, 1/(2r) on
+            the two cell edges when r is even (they fall on fine rows), 0 outside."""
     n = np.arange(-(2 * r - 1), 2 * r)
-    return B(n / r) / r
+    if kind == 0:
+        return B(n / r) / r
+    if kind == 1:
+        d = np.where(2 * np.abs(n) < r, 1.0 / r, 0.0)
+        return np.where(2 * np.abs(n) == r, 0.5 / r, d)
+    raise ValueError(f"unknown decimation filter {kind}")
 
 
-def decimation_response(r: int, k_theta: int) -> np.ndarray:
+def decimation_response(r: int, k_theta: int, kind: int = 0) -> np.ndarray:
     """D_hat at coarse frequencies kt = 0..K/2: sum_n d_n cos(2 pi kt n / (r K))."""
-    d = decimation_taps(r)
+    d = decimation_taps(r, kind)
     n = np.arange(-(2 * r - 1), 2 * r)
     kt = np.arange(k_theta // 2 + 1)
     return (d[None, :] * np.cos(2.0 * np.pi * np.outer(kt, n) / (r * k_theta))).sum(axis=1)
@@ -71,7 +81,7 @@ def gauss_legendre_panels(a: float, b: float, n_panels: int, n_nodes: int = GL_N
 def zeta_hat_half(geom, kt_max=None, kr_max=None) -> np.ndarray:
     """zeta_hat(k_theta, k_rho) for k_theta = 0..K/2 and k_rho = 0..N_rho/2 (complex128)."""
     beta = geom.beta
-    P = geom.k_theta * geom.dtheta
+    P = geom.k_theta * geom.dtheta_c
     L = geom.L
     nkt = geom.k_theta // 2 + 1 if kt_max is None else kt_max + 1
     nkr = geom.n_rho // 2 + 1 if kr_max is None else kr_max + 1
@@ -100,7 +110,7 @@ def multiplier_half(geom, zeta_half=None) -> np.ndarray:
         zeta_half = zeta_hat_half(geom)
     kr = np.arange(geom.n_rho // 2 + 1)
     bh = B_hat(kr / geom.n_rho)
-    dh = decimation_response(geom.r_dec, geom.k_theta)
+    dh = decimation_response(geom.r_dec, geom.k_theta, geom.dec_filter)
     H = zeta_half / (dh[:, None] * bh[None, :])
     H[:, -1] = H[:, -1].real
     return H

@@ -26,7 +26,10 @@ each a linear map, in the paper's order and notation:
 Readings (where the paper is silent or garbled; see also geometry.py,
 bspline.py and kernel.py):
   * S4 filter (unspecified in the paper): d_n = B(n/r)/r, |n| < 2r, applied to
-    the fine rows at phi_i + n*Delta theta/r, and divided out in H;
+    the fine rows at phi_i + n*Delta theta_c/r, and divided out in H (or the box
+    of one coarse cell, geom.dec_filter = 1; on a lattice of spacing Delta
+    theta_c = Delta theta / q_theta, geom.q_theta = 2, the owned rows sit on every
+    other lattice row);
   * S6 convolution mode "fft" (numpy FFTs) or "direct" (the circulant sum with
     the real kernel ifft2(H), for tiny sizes);
   * R# is the exact transpose of R weighted by the grids' quadrature weights:
@@ -53,7 +56,6 @@ import math
 import numpy as np
 
 from . import bspline
-from .geometry import HALO
 from .kernel import decimation_taps, multiplier_full
 
 MASK_EPS = 1e-9  # samples closer than this (in e^rho) to the boundary of D count as outside
@@ -62,7 +64,8 @@ _H_CACHE: dict = {}
 
 
 def _H(geom):
-    key = (geom.n, geom.n_theta, geom.n_s, geom.m, geom.n_rho, geom.k_theta, geom.r_dec)
+    key = (geom.n, geom.n_theta, geom.n_s, geom.m, geom.n_rho, geom.k_theta, geom.r_dec, geom.dec_filter,
+           geom.q_theta)
     if key not in _H_CACHE:
         _H_CACHE[key] = multiplier_full(geom)
     return _H_CACHE[key]
@@ -139,7 +142,7 @@ def eval_taus(geom, p):
         thp = math.pi * nu / (geom.n_theta * geom.m)
         st = -s if wrap else s
         tau = (np.log(a_R * st + (1.0 - a_R) * math.cos(thp)) - rho0) / geom.d_rho
-        out.append((HALO + pos, j, tau))
+        out.append((geom.lattice_row(pos), j, tau))
     return out
 
 
@@ -174,8 +177,8 @@ def _partition_forward(geom, c, p, mode):
     ti, q, X, Y = fine_sample_points(geom, p)
     v = np.zeros((nfine, geom.n_rho))
     v[ti, q] = _bicubic_matrix_apply(c, X, Y)                       # S3
-    n_sup_p = len(geom.partition_rows(p)) + 2 * HALO
-    d = decimation_taps(r)
+    n_sup_p = geom.n_sup_p(p)
+    d = decimation_taps(r, geom.dec_filter)
     u = np.zeros((n_sup_p, geom.n_rho))
     for i in range(n_sup_p):                                         # S4
         # fine rows t = r*i + n, n = -(2r-1)..2r-1, stored at index t - t[0]
@@ -203,7 +206,7 @@ def radon_fwd(geom, f, mode="fft"):
 def _partition_adjoint(geom, g, p, mode):
     """Partition p's share of R^T g before the prefilter: S3^T S4^T S5^T S6^T S7^T."""
     r = geom.r_dec
-    d = decimation_taps(r)
+    d = decimation_taps(r, geom.dec_filter)
     Nr = geom.n_rho
     C = np.zeros((geom.k_theta, Nr))
     for i, j, tau in eval_taus(geom, p):                             # S7^T
@@ -211,7 +214,7 @@ def _partition_adjoint(geom, g, p, mode):
         for a in range(4):
             C[i] += np.bincount((k - 1 + a) % Nr, weights=wts[a] * g[j], minlength=Nr) / geom.a_R
     Wt = _conv(geom, C, conj=True, mode=mode)                        # S6^T
-    n_sup_p = len(geom.partition_rows(p)) + 2 * HALO
+    n_sup_p = geom.n_sup_p(p)
     w = Wt[:n_sup_p] * np.exp(geom.rho_nodes())[None, :]            # S5^T
     t = geom.fine_rows(p)
     v = np.zeros((t.size, Nr))
