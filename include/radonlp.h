@@ -79,14 +79,20 @@ typedef enum { RL_FILTER_RAMLAK = 0, RL_FILTER_COSINE = 1, RL_FILTER_SHEPP_LOGAN
  *   m        angular partitions M >= 3, beta = pi/M (sec. 2)
  *   n_rho    rho-FFT length, a power of two >= ceil(log a_r / log(1 - 2 a_R / N))
  *            (sec. 3 eq. vrho), <= 8192
- *   k_theta  theta-FFT length, a power of two >= 2*ceil(N_theta/M) (sec. 5, the grid
- *            of size 2 N_theta / M), >= n_own + 4, <= 2048
- *   r_dec    fine angular oversampling of the log-polar grid: Delta theta / r_dec <=
- *            2 a_R / N (sec. 3, before eq. Lopolargrid_f), <= 32
+ *   k_theta  theta-FFT length, a power of two >= 2*q_theta*ceil(N_theta/M) (sec. 5, the
+ *            grid of size 2 N_theta / M, in lattice rows), >= n_sup = q_theta*(n_own - 1) + 5
+ *            (the lattice rows of the owned rows plus two on each side), <= 2048
+ *   r_dec    fine angular oversampling of the log-polar grid: (Delta theta / q_theta) / r_dec
+ *            <= 2 a_R / N (sec. 3, before eq. Lopolargrid_f), <= 32
  *   dec_filter  theta low-pass used to go from the fine grid to the coarse one
- *            (Algorithm 1 step 4; not specified by the paper); 0 = cubic B-spline FIR
- *            d_n = B(n/r)/r, |n| < 2r, whose response is divided out in the Fourier
- *            multiplier.  No other value is accepted.
+ *            (Algorithm 1 step 4; not specified by the paper), its response divided out in
+ *            the Fourier multiplier: 0 = cubic B-spline FIR d_n = B(n/r)/r, |n| < 2r;
+ *            1 = box of one coarse cell, d_n = 1/r for |n| < r/2 and 1/(2r) at |n| = r/2
+ *            (the cell's edges, present for even r).  Other values: RL_ERR_GEOMETRY.
+ *   q_theta  coarse lattice spacing Delta theta / q_theta (1: the sinogram's spacing, the grid
+ *            Omega_p of sec. 3 eq. Lopolargrid_polar; 2: twice as fine in theta, with the
+ *            owned sinogram rows on every other lattice row).  1 or 2; the Algorithm 2 entry
+ *            points (radon_bp_lp, fbp_lp) need 1.
  */
 typedef struct {
   int32_t n;
@@ -97,6 +103,7 @@ typedef struct {
   int32_t k_theta;
   int32_t r_dec;
   int32_t dec_filter;
+  int32_t q_theta;
 } rl_geom;
 
 typedef struct rl_plan rl_plan;
@@ -112,12 +119,21 @@ typedef struct rl_plan rl_plan;
  *                    [32, 4096]
  *   fwd_patch_split  1: forward gather tiles whose image box fits the small LDS patch run with
  *                    it (more blocks per CU), the others with the large one; 0: all large
- * Defaults (rl_plan_create): 0, 1, 512, 1. */
+ *   fwd_xcd_order    1: blocks of the forward gather are ordered so that each XCD (with its own
+ *                    L2) runs one contiguous run of the tile list (neighbouring tiles read
+ *                    overlapping image boxes); 0: launch order
+ *   adj_direct       1: the back-projection's Cartesian splat adds every sample's 16 weighted
+ *                    values to its LDS tile directly; 0: it sums them in a register footprint that
+ *                    follows the ray and adds only what the footprint leaves behind.  The two
+ *                    add the same FP32 terms in FP64 in a different order.
+ * Defaults (rl_plan_create): 0, 1, 512, 1, 1, 0. */
 typedef struct {
   int32_t theta_cols;
   int32_t theta_xcd_order;
   int32_t prefilter_rows;
   int32_t fwd_patch_split;
+  int32_t fwd_xcd_order;
+  int32_t adj_direct;
 } rl_tune;
 
 /* Read / replace the plan's launch parameters.  rl_plan_set_tuning validates *tune
@@ -134,7 +150,7 @@ size_t rl_tune_workspace_bytes(const rl_plan* plan, int32_t batch);
  * candidate timed with HIP events over three runs after one warm-up, keeping the fastest), and
  * set the best on the plan.  If cache_path is not NULL, the result is first looked up in that
  * file and, when absent, appended to it: one JSON object per line with the key
- * "<arch> rocm=<HIP version> n=.. n_theta=.. n_s=.. m=.. n_rho=.. k_theta=.. r_dec=.. dec_filter=..
+ * "<arch> rocm=<HIP version> n=.. n_theta=.. n_s=.. m=.. n_rho=.. k_theta=.. r_dec=.. dec_filter=.. q_theta=..
  * batch=..", the four fields and the measured R and R# times.  Synchronous on `stream` (it waits
  * for its own work), not capturable; not concurrent with other calls using the plan.  Errors:
  * RL_ERR_WORKSPACE if ws_bytes < rl_tune_workspace_bytes(plan, batch); RL_ERR_INVALID_ARG for a
@@ -142,11 +158,12 @@ size_t rl_tune_workspace_bytes(const rl_plan* plan, int32_t batch);
 rl_status rl_plan_autotune(rl_plan* plan, int32_t batch, void* d_ws, size_t ws_bytes, hipStream_t stream,
                            const char* cache_path);
 
-/* Fill *out with the default geometry for (n, n_theta, n_s, m): n_rho and k_theta are
- * the smallest powers of two meeting their bounds, r_dec the smallest integer meeting
- * its bound, dec_filter = 0.  Host-only; touches no device.  Returns RL_ERR_GEOMETRY if
- * no valid geometry exists within the limits above. */
-rl_status rl_geom_default(int32_t n, int32_t n_theta, int32_t n_s, int32_t m, rl_geom* out);
+/* Fill *out with the default geometry for (n, n_theta, n_s, m) on a coarse lattice q_theta (1 or
+ * 2) times finer than the sinogram rows: n_rho and k_theta are the smallest powers of two
+ * meeting their bounds, r_dec the smallest integer meeting its bound, dec_filter = 0.
+ * Host-only; touches no device.  Returns RL_ERR_GEOMETRY if no valid geometry exists within the
+ * limits above. */
+rl_status rl_geom_default(int32_t n, int32_t n_theta, int32_t n_s, int32_t m, int32_t q_theta, rl_geom* out);
 
 /* Validate *geom and build a plan on the current device: partition tables, masks, the
  * Fourier multiplier H = zeta_hat / (B_hat_rho D_hat_theta) of sec. 3 eq. (exprcoef1)

@@ -75,6 +75,7 @@ class RlGeom(ctypes.Structure):
         ("k_theta", ctypes.c_int32),
         ("r_dec", ctypes.c_int32),
         ("dec_filter", ctypes.c_int32),
+        ("q_theta", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -87,6 +88,8 @@ class RlTune(ctypes.Structure):
         ("theta_xcd_order", ctypes.c_int32),
         ("prefilter_rows", ctypes.c_int32),
         ("fwd_patch_split", ctypes.c_int32),
+        ("fwd_xcd_order", ctypes.c_int32),
+        ("adj_direct", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -114,7 +117,7 @@ def load(path: str = LIB_PATH):
         )
     lib = ctypes.CDLL(path)
     c_int32, c_size_t, c_void_p = ctypes.c_int32, ctypes.c_size_t, ctypes.c_void_p
-    lib.rl_geom_default.argtypes = [c_int32, c_int32, c_int32, c_int32, ctypes.POINTER(RlGeom)]
+    lib.rl_geom_default.argtypes = [c_int32, c_int32, c_int32, c_int32, c_int32, ctypes.POINTER(RlGeom)]
     lib.rl_geom_default.restype = c_int32
     lib.rl_plan_create.argtypes = [ctypes.POINTER(RlGeom), ctypes.POINTER(c_void_p)]
     lib.rl_plan_create.restype = c_int32
@@ -182,8 +185,8 @@ def check(func: str, status: int):
         raise RadonLibError(func, status, msg)
 
 
-def geom_default(n, n_theta, n_s, m=4) -> RlGeom:
+def geom_default(n, n_theta, n_s, m=4, q_theta=1) -> RlGeom:
     lib = load()
     g = RlGeom()
-    check("rl_geom_default", lib.rl_geom_default(n, n_theta, n_s, m, ctypes.byref(g)))
+    check("rl_geom_default", lib.rl_geom_default(n, n_theta, n_s, m, q_theta, ctypes.byref(g)))
     return g

@@ -285,6 +285,36 @@ __device__ __forceinline__ void splat_walk(const SegWalk& sw, double* acc, const
   }
 }
 
+// Walk one segment without a register footprint: each sample is rebuilt as in splat_walk and
+// its 16 weighted values go straight to the FP64 LDS tile.  Every lane runs the same
+// instructions at every sample (no footprint moves), at the price of 16 LDS atomics per sample.
+__device__ __forceinline__ void splat_walk_direct(const SegWalk& sw, double* acc, const float* rows,
+                                                  const double* erho, int qlo) {
+  // LDS index of pixel (x, y), unwrapped index coordinates: (y - uy0 + kAHalo) kAP + x - ux0 + kAHalo
+  const int obase = (kAHalo - 1 - sw.uy0) * kAP + (kAHalo - 1 - sw.ux0);
+  for (int q = sw.qbeg; q <= sw.qend; ++q) {
+    const int qi = q - qlo;
+    const double E = erho[qi];
+    // (dw carries the weights' 1/36)
+    const float V = sw.dw[0] * rows[sw.roff[0] + qi] + sw.dw[1] * rows[sw.roff[1] + qi] +
+                    sw.dw[2] * rows[sw.roff[2] + qi] + sw.dw[3] * rows[sw.roff[3] + qi];
+    const double X = sw.X0 + E * sw.cx, Y = sw.Y0 + E * sw.cy;
+    const double fx = floor(X), fy = floor(Y);
+    // as in splat_walk, the clamp only keeps the adds inside the halo
+    const int kx = min(max((int)fx, sw.ux0 - 3), sw.ux1 + 1), ky = min(max((int)fy, sw.uy0 - 3), sw.uy1 + 1);
+    float wx[4], wy[4];
+    bspline_w6((float)(X - fx), wx);
+    bspline_w6((float)(Y - fy), wy);
+    double* a = acc + obase + ky * kAP + kx;  // pixel (kx - 1, ky - 1)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float vy = V * wy[j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) atomicAdd(a + j * kAP + i, (double)(vy * wx[i]));
+    }
+  }
+}
+
 // ---- splat passes, built once per plan
 // A pass is one partition m, one periodic shift (sx, sy) of one tile and up to kARows fine
 // rays ta .. ta + nrows - 1, laid out in ray slots (slot of ray k: (k % kRayGap) * ng +
@@ -338,7 +368,7 @@ __global__ __launch_bounds__(kBThreads) void k_adj_build(DevPlan P, int2* __rest
           phmin = fmin(phmin, ph);
           phmax = fmax(phmax, ph);
         }
-        const double fstep = P.dtheta / r;
+        const double fstep = P.dtheta_c / r;
         const int ta = max(P.t_min, (int)floor((phmin - P.phi0[m]) / fstep) - 1);
         const int tb = min(P.t_min + P.n_fine - 1, (int)ceil((phmax - P.phi0[m]) / fstep) + 1);
         for (int tc = ta; tc <= tb; tc += kARows) {
@@ -529,6 +559,7 @@ rl_status build_adj_passes(rl_plan* p) {
 // of its rays are copied to LDS with e^rho for one window of rho indices at a time (one
 // window usually covers the pass), and every thread walks at most one segment.  The FP64
 // tile (with its halo) collects all partitions and is written once.
+template <bool DIRECT>
 __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const float* __restrict__ U,
                                                               float* __restrict__ cbar) {
   // FP64: LDS float atomics are slow on this target.
@@ -652,7 +683,8 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
           sw.dw[i] = ok ? dwv[i] * (1.0f / 36.0f) : 0.f;
           sw.roff[i] = (min(max(row, cg0), cg1) - cg0) * span;
         }
-        splat_walk(sw, acc, us, es, wq4);
+        if (DIRECT) splat_walk_direct(sw, acc, us, es, wq4);
+        else splat_walk(sw, acc, us, es, wq4);
       }
     }
   }
@@ -668,7 +700,10 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
 rl_status launch_lp2cart_adj(const rl_plan* p, const float* U, float* cbar, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   dim3 grid((d.n + kTile - 1) / kTile, (d.n + kTile - 1) / kTile, batch);
-  RL_LAUNCH("k_lp2cart_adj", k_lp2cart_adj, grid, dim3(kAThreads), 0, s, d, U, cbar);
+  if (p->tune.adj_direct)
+    RL_LAUNCH("k_lp2cart_adj", k_lp2cart_adj<true>, grid, dim3(kAThreads), 0, s, d, U, cbar);
+  else
+    RL_LAUNCH("k_lp2cart_adj", k_lp2cart_adj<false>, grid, dim3(kAThreads), 0, s, d, U, cbar);
   return check_launch("k_lp2cart_adj");
 }
 
@@ -782,7 +817,7 @@ rl_status adjoint_chain(const rl_plan* plan, Slices<const float> sino, Slices<fl
   float2* A = (float2*)(w + L.off[3]);
   rl_status st;
   if ((st = launch_splat_rfft(plan, sino, A, batch, s)) != RL_OK) return st;
-  if ((st = launch_theta_conv(plan, A, d.n_own, kHalo, Bs, d.n_sup, 0, true, batch, s)) != RL_OK) return st;
+  if ((st = launch_theta_conv(plan, A, d.n_own, kHalo, d.q, Bs, d.n_sup, 0, 1, true, batch, s)) != RL_OK) return st;
   if ((st = launch_irfft_scale(plan, Bs, U, batch, s)) != RL_OK) return st;
   if ((st = launch_lp2cart_adj(plan, U, cbar, batch, s)) != RL_OK) return st;
   const double scale = transpose ? 1.0 : (d.dtheta * d.ds) / (d.dx * d.dx);  // w_S / w_X for R#

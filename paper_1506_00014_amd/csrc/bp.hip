@@ -270,7 +270,7 @@ static rl_status bp_lp_chain(const rl_plan* plan, const float* sino, float* img,
     RL_LAUNCH("k_bp_rows_rfft", k_bp_rows_rfft, dim3(d.n_own, batch * d.m), dim3(kThreads), lds, s, d, sino, A);
     if ((st = check_launch("k_bp_rows_rfft")) != RL_OK) return st;
   }
-  if ((st = launch_theta_conv(plan, A, d.n_own, kHalo, Bs, d.n_sup, 0, false, batch, s, d.Hbp)) != RL_OK) return st;
+  if ((st = launch_theta_conv(plan, A, d.n_own, kHalo, 1, Bs, d.n_sup, 0, 1, false, batch, s, d.Hbp)) != RL_OK) return st;
   if ((st = launch_irfft_rows(plan, Bs, U, batch * d.m * d.n_sup, s)) != RL_OK) return st;
   dim3 grid((d.n + kGx - 1) / kGx, (d.n + kGy - 1) / kGy, (batch + kBch - 1) / kBch);
   if (batch >= kStageMin)
@@ -286,6 +286,8 @@ using namespace rl;
 
 extern "C" rl_status radon_bp_lp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, void* d_ws,
                                  size_t ws_bytes, hipStream_t stream) {
+  if (plan && plan->d.q != 1)
+    return fail(RL_ERR_GEOMETRY, "radon_bp_lp needs q_theta = 1 (its lattice rows are the sinogram rows)");
   rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_BP_LP);
   if (st != RL_OK || batch == 0) return st;
   return bp_lp_chain(plan, d_sino, d_img, batch, d_ws, RL_OP_BP_LP, stream);
@@ -295,6 +297,8 @@ extern "C" rl_status fbp_lp(const rl_plan* plan, const float* d_sino, float* d_i
                             void* d_ws, size_t ws_bytes, hipStream_t stream) {
   if (filter != RL_FILTER_RAMLAK && filter != RL_FILTER_COSINE && filter != RL_FILTER_SHEPP_LOGAN)
     return fail(RL_ERR_INVALID_ARG, "unknown filter");
+  if (plan && plan->d.q != 1)
+    return fail(RL_ERR_GEOMETRY, "fbp_lp needs q_theta = 1 (its lattice rows are the sinogram rows)");
   rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_FBP_LP);
   if (st != RL_OK || batch == 0) return st;
   const WsLayout L = workspace_layout(plan, batch, RL_OP_FBP_LP);

@@ -171,15 +171,21 @@ __device__ __forceinline__ float bicubic_at(double X, double Y, int n, Tap tap) 
 //    around it, times e^rho.
 template <int PATCH>
 __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __restrict__ tiles,
-                                                        const float* __restrict__ c, float* __restrict__ u) {
+                                                        const float* __restrict__ c, float* __restrict__ u,
+                                                        int xcd_order) {
   extern __shared__ float smem[];
   float* patch = smem;
   float* vbuf = smem + PATCH;
   // tile (m, by, bx) from the plan's list for this patch size; slice from blockIdx.y
   const int gx = (P.n_rho + kFQ - 1) / kFQ, gy = (P.n_sup + kFRows - 1) / kFRows;
-  const int tile = tiles[blockIdx.x];
+  // (list entry, slice) of this block; with xcd_order each XCD takes one contiguous run of
+  // them, so tiles that read overlapping image boxes share that XCD's L2
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  const int lid = xcd_order ? xcd_block(bid, gridDim.x * gridDim.y) : bid;
+  const int b = lid / gridDim.x;
+  const int tile = tiles[lid - b * gridDim.x];
   const int bx = tile % gx, by = (tile / gx) % gy, m = tile / (gx * gy);
-  const int b = blockIdx.y, bm = b * P.m + m;
+  const int bm = b * P.m + m;
   const int q0 = bx * kFQ;
   const int i0 = by * kFRows;
   const int i1 = min(i0 + kFRows, P.n_sup);
@@ -415,12 +421,12 @@ rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, 
   const int n_large = d.ftiles_small + d.ftiles_large - n_small;
   if (n_small > 0) {
     hipLaunchKernelGGL(k_cart2lp<kFPatchSmall>, dim3(n_small, batch), dim3(kFThreads),
-                       cart2lp_lds(d, kFPatchSmall), s, d, d.ftiles, c, u);
+                       cart2lp_lds(d, kFPatchSmall), s, d, d.ftiles, c, u, p->tune.fwd_xcd_order);
     st = check_launch("k_cart2lp");
   }
   if (st == RL_OK && n_large > 0) {
     hipLaunchKernelGGL(k_cart2lp<kFPatch>, dim3(n_large, batch), dim3(kFThreads), cart2lp_lds(d, kFPatch), s,
-                       d, d.ftiles + n_small, c, u);
+                       d, d.ftiles + n_small, c, u, p->tune.fwd_xcd_order);
     st = check_launch("k_cart2lp");
   }
   prof_close(slot, s);
@@ -492,8 +498,9 @@ rl_status launch_irfft_rows(const rl_plan* p, const float2* in, float* out, int 
 // twiddles W_K^{n2 k1} are copied to LDS once per block (n2-major, as stage A reads them).
 template <int K1, int K2>
 __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2* __restrict__ in, int in_rows,
-                                                         int in_off, float2* __restrict__ out, int out_rows,
-                                                         int out_off, int conj, int cw, int xcd_order) {
+                                                         int in_off, int in_step, float2* __restrict__ out,
+                                                         int out_rows, int out_off, int out_step, int conj, int cw,
+                                                         int xcd_order) {
   extern __shared__ float2 sh[];
   constexpr int K = K1 * K2;
   constexpr int RS = K2 + 1;           // padded stride between k1 rows
@@ -521,8 +528,11 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
     if (act) {
 #pragma unroll
       for (int n1 = 0; n1 < K1; ++n1) {
-        const int ir = K2 * n1 + n2 - in_off;
-        x[n1] = (ir >= 0 && ir < in_rows) ? src[(size_t)ir * P.ld + col] : make_float2(0.f, 0.f);
+        // lattice row K2 n1 + n2 holds input row ir if it is in_off + in_step * ir
+        const int lr = K2 * n1 + n2 - in_off;
+        const int ir = in_step == 1 ? lr : lr >> 1;
+        const bool hit = lr >= 0 && (in_step == 1 || (lr & 1) == 0) && ir < in_rows;
+        x[n1] = hit ? src[(size_t)ir * P.ld + col] : make_float2(0.f, 0.f);
       }
       reg_fft<K1, false>(x, P.tw, P.tw_len);
     }
@@ -584,8 +594,9 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
       float2* dst = out + (size_t)bm * out_rows * P.ld;
 #pragma unroll
       for (int n1 = 0; n1 < K1; ++n1) {
-        const int orow = K2 * n1 + n2 - out_off;
-        if (orow >= 0 && orow < out_rows) dst[(size_t)orow * P.ld + col] = x[n1];
+        const int lr = K2 * n1 + n2 - out_off;
+        const int orow = out_step == 1 ? lr : lr >> 1;
+        if (lr >= 0 && (out_step == 1 || (lr & 1) == 0) && orow < out_rows) dst[(size_t)orow * P.ld + col] = x[n1];
       }
     }
   }
@@ -632,9 +643,11 @@ rl_status prepare_forward_launches(const rl_plan* p) {
 }
 
 template <int K1, int K2>
-static rl_status launch_theta_conv_t(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out,
-                                     int out_rows, int out_off, bool conj, int batch, hipStream_t s,
-                                     const float2* H) {
+static rl_status launch_theta_conv_t(const rl_plan* p, const float2* in, int in_rows, int in_off, int in_step,
+                                     float2* out, int out_rows, int out_off, int out_step, bool conj, int batch,
+                                     hipStream_t s, const float2* H) {
+  if ((in_step != 1 && in_step != 2) || (out_step != 1 && out_step != 2))
+    return fail(RL_ERR_INTERNAL, "theta pass row step must be 1 or 2");
   DevPlan d = p->d;
   if (H) d.H = H;
   const int cw = theta_cw<K1, K2>(p->tune.theta_cols);
@@ -642,23 +655,24 @@ static rl_status launch_theta_conv_t(const rl_plan* p, const float2* in, int in_
   rl_status st = ensure_dyn_lds((const void*)k_theta_conv<K1, K2>, lds, "hipFuncSetAttribute(k_theta_conv)");
   if (st != RL_OK) return st;
   dim3 grid((d.nc + 1 + cw - 1) / cw, batch * d.m);
-  RL_LAUNCH("k_theta_conv", (k_theta_conv<K1, K2>), grid, dim3(kThreads), lds, s, d, in, in_rows, in_off, out,
-            out_rows, out_off, conj ? 1 : 0, cw, p->tune.theta_xcd_order);
+  RL_LAUNCH("k_theta_conv", (k_theta_conv<K1, K2>), grid, dim3(kThreads), lds, s, d, in, in_rows, in_off, in_step,
+            out, out_rows, out_off, out_step, conj ? 1 : 0, cw, p->tune.theta_xcd_order);
   return check_launch("k_theta_conv");
 }
 
-rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out, int out_rows,
-                            int out_off, bool conj, int batch, hipStream_t s, const float2* H) {
+rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int in_off, int in_step, float2* out,
+                            int out_rows, int out_off, int out_step, bool conj, int batch, hipStream_t s,
+                            const float2* H) {
   switch (p->d.k_theta) {
-    case 8: return launch_theta_conv_t<8, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
-    case 16: return launch_theta_conv_t<16, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
-    case 32: return launch_theta_conv_t<32, 1>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
-    case 64: return launch_theta_conv_t<32, 2>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
-    case 128: return launch_theta_conv_t<32, 4>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
-    case 256: return launch_theta_conv_t<32, 8>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
-    case 512: return launch_theta_conv_t<32, 16>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
-    case 1024: return launch_theta_conv_t<32, 32>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
-    case 2048: return launch_theta_conv_t<32, 64>(p, in, in_rows, in_off, out, out_rows, out_off, conj, batch, s, H);
+    case 8: return launch_theta_conv_t<8, 1>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
+    case 16: return launch_theta_conv_t<16, 1>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
+    case 32: return launch_theta_conv_t<32, 1>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
+    case 64: return launch_theta_conv_t<32, 2>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
+    case 128: return launch_theta_conv_t<32, 4>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
+    case 256: return launch_theta_conv_t<32, 8>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
+    case 512: return launch_theta_conv_t<32, 16>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
+    case 1024: return launch_theta_conv_t<32, 32>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
+    case 2048: return launch_theta_conv_t<32, 64>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
     default: return fail(RL_ERR_INTERNAL, "unsupported k_theta");
   }
 }
@@ -754,7 +768,7 @@ rl_status forward_chain(const rl_plan* plan, Slices<const float> img, Slices<flo
   if ((st = launch_cart2lp(plan, c, stop_stage == RL_STAGE_LOGPOLAR ? stage_out : u, batch, s)) != RL_OK) return st;
   if (stop_stage == RL_STAGE_LOGPOLAR) return RL_OK;
   if ((st = launch_rfft_rows(plan, u, A, batch * d.m * d.n_sup, s)) != RL_OK) return st;
-  if ((st = launch_theta_conv(plan, A, d.n_sup, 0, Bs, d.n_own, kHalo, false, batch, s)) != RL_OK) return st;
+  if ((st = launch_theta_conv(plan, A, d.n_sup, 0, 1, Bs, d.n_own, kHalo, d.q, false, batch, s)) != RL_OK) return st;
   if (stop_stage == RL_STAGE_CONV) return launch_irfft_rows(plan, Bs, stage_out, batch * d.m * d.n_own, s);
   return launch_irfft_eval(plan, Bs, sino, batch, out_scale, s);
 }

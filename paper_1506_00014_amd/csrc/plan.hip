@@ -42,12 +42,16 @@ long rho_bound(int n, int m) {
   return (long)std::ceil(std::log(a_r) / std::log(1.0 - 2.0 * a_R / n));
 }
 
-long r_bound(int n, int n_theta, int m) {
-  // Delta theta / r <= 2 a_R / N (sec. 3, the angular step before eq. Lopolargrid_f)
+long r_bound(int n, int n_theta, int m, int q) {
+  // Delta theta_c / r <= 2 a_R / N (sec. 3, the angular step before eq. Lopolargrid_f), with
+  // Delta theta_c = Delta theta / q the coarse lattice spacing
   double a_R, a_r;
   partition_constants(m, &a_R, &a_r);
-  return (long)std::ceil((M_PI / n_theta) / (2.0 * a_R / n) - 1e-12);
+  return (long)std::ceil((M_PI / ((double)n_theta * q)) / (2.0 * a_R / n) - 1e-12);
 }
+
+// Lattice rows spanned by n consecutive owned rows on a lattice q times finer than the sinogram.
+int lattice_rows(int n, int q) { return n > 0 ? q * (n - 1) + 1 : 0; }
 
 // Ownership of sinogram row j (eq. Radon_all_pb, rounding half up, exact in integers):
 // partition, wrap flag, and nu with theta'_j = pi nu / (N_theta M).
@@ -84,6 +88,17 @@ double bspline(double x) {
   if (a < 1.0) return (3.0 * a * a * a - 6.0 * a * a + 4.0) / 6.0;
   if (a < 2.0) return (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0;
   return 0.0;
+}
+
+// Taps of the theta low-pass of Algorithm 1 step 4 (the paper leaves it open), n = -(2r-1) ..
+// 2r-1, sum 1: kind 0 the cubic B-spline d_n = B(n/r)/r; kind 1 the box of one coarse cell
+// sampled by the trapezoid rule on the fine rows (1/r inside, 1/(2r) on the cell's two edges,
+// which fall on fine rows when r is even).
+double dec_tap(int kind, int n, int r) {
+  if (std::abs(n) >= 2 * r) return 0.0;
+  if (kind == 0) return bspline((double)n / r) / r;
+  if (2 * std::abs(n) < r) return 1.0 / r;
+  return 2 * std::abs(n) == r ? 0.5 / r : 0.0;
 }
 
 // Gauss-Legendre nodes/weights on [-1, 1] by Newton's method on the Legendre recurrence.
@@ -178,11 +193,15 @@ rl_status validate(const rl_geom& g) {
   }
   if (!is_pow2(g.k_theta) || g.k_theta < 8 || g.k_theta > 2048)
     return fail(RL_ERR_GEOMETRY, "k_theta must be a power of two in [8, 2048]");
-  if (g.k_theta < 2 * ((g.n_theta + g.m - 1) / g.m) || g.k_theta < n_own + 2 * kHalo)
-    return fail(RL_ERR_GEOMETRY, "k_theta must be >= 2 ceil(n_theta/m) and >= n_own + 4");
-  if (g.r_dec < r_bound(g.n, g.n_theta, g.m) || g.r_dec > 32)
-    return fail(RL_ERR_GEOMETRY, "r_dec must satisfy dtheta / r_dec <= 2 a_R / n and be <= 32");
-  if (g.dec_filter != 0) return fail(RL_ERR_GEOMETRY, "dec_filter must be 0");
+  if (g.q_theta != 1 && g.q_theta != 2) return fail(RL_ERR_GEOMETRY, "q_theta must be 1 or 2");
+  if (g.k_theta < 2 * g.q_theta * ((g.n_theta + g.m - 1) / g.m) ||
+      g.k_theta < lattice_rows(n_own, g.q_theta) + 2 * kHalo)
+    return fail(RL_ERR_GEOMETRY,
+                "k_theta must be >= 2 q_theta ceil(n_theta/m) and >= q_theta (n_own - 1) + 5");
+  if (g.r_dec < r_bound(g.n, g.n_theta, g.m, g.q_theta) || g.r_dec > 32)
+    return fail(RL_ERR_GEOMETRY, "r_dec must satisfy (dtheta / q_theta) / r_dec <= 2 a_R / n and be <= 32");
+  if (g.dec_filter != 0 && g.dec_filter != 1)
+    return fail(RL_ERR_GEOMETRY, "dec_filter must be 0 (cubic B-spline) or 1 (box)");
   return RL_OK;
 }
 
@@ -315,9 +334,10 @@ WsLayout workspace_layout(const rl_plan* plan, int batch, rl_op op) {
 
 using namespace rl;
 
-extern "C" rl_status rl_geom_default(int32_t n, int32_t n_theta, int32_t n_s, int32_t m, rl_geom* out) {
+extern "C" rl_status rl_geom_default(int32_t n, int32_t n_theta, int32_t n_s, int32_t m, int32_t q_theta,
+                                    rl_geom* out) {
   if (!out) return fail(RL_ERR_INVALID_ARG, "out is NULL");
-  if (n < 8 || (n & 1) || n > 8192 || m < 3 || m > kMaxPart || n_theta < m || n_s < 2)
+  if (n < 8 || (n & 1) || n > 8192 || m < 3 || m > kMaxPart || n_theta < m || n_s < 2 || (q_theta != 1 && q_theta != 2))
     return fail(RL_ERR_GEOMETRY, "no default geometry for these sizes");
   rl_geom g{};
   g.n = n;
@@ -328,9 +348,11 @@ extern "C" rl_status rl_geom_default(int32_t n, int32_t n_theta, int32_t n_s, in
   int n_own = 0;
   auto rows = partition_rows(n_theta, m);
   for (auto& r : rows) n_own = std::max<int>(n_own, (int)r.size());
-  g.k_theta = std::max(8, next_pow2(std::max<long>(2L * ((n_theta + m - 1) / m), n_own + 2 * kHalo)));
-  g.r_dec = (int)r_bound(n, n_theta, m);
+  g.k_theta = std::max(8, next_pow2(std::max<long>(2L * q_theta * ((n_theta + m - 1) / m),
+                                                   lattice_rows(n_own, q_theta) + 2 * kHalo)));
+  g.r_dec = (int)r_bound(n, n_theta, m, q_theta);
   g.dec_filter = 0;
+  g.q_theta = q_theta;
   rl_status st = validate(g);
   if (st != RL_OK) return st;
   *out = g;
@@ -355,7 +377,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   rl_plan* plan = new rl_plan();
   plan->g = g;
   plan->device = dev;
-  plan->tune = rl_tune{0, 1, 512, 1};
+  plan->tune = rl_tune{0, 1, 512, 1, 1, 0};
   DevPlan& d = plan->d;
   std::memset(&d, 0, sizeof(d));
   d.n = g.n;
@@ -365,6 +387,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   d.n_rho = g.n_rho;
   d.k_theta = g.k_theta;
   d.r = g.r_dec;
+  d.q = g.q_theta;
   double a_R, a_r;
   partition_constants(g.m, &a_R, &a_r);
   const double L = -std::log(a_r);
@@ -373,13 +396,14 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   d.dx = 2.0 / g.n;
   d.ds = 2.0 / g.n_s;
   d.dtheta = M_PI / g.n_theta;
+  d.dtheta_c = d.dtheta / g.q_theta;
   d.d_rho = L / g.n_rho;
   d.rho0 = (1.0 - g.n_rho) * d.d_rho;
   auto rows = partition_rows(g.n_theta, g.m);
   int n_own = 0;
   for (auto& r : rows) n_own = std::max<int>(n_own, (int)r.size());
   d.n_own = n_own;
-  d.n_sup = n_own + 2 * kHalo;
+  d.n_sup = lattice_rows(n_own, g.q_theta) + 2 * kHalo;
   const int r = g.r_dec;
   d.t_min = -(2 * r - 1);
   d.n_fine = r * (d.n_sup - 1) + 4 * r - 1;
@@ -393,7 +417,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
     const double mb = p * d.beta;
     d.X0[p] = (1.0 - (1.0 - a_R) * std::cos(mb) / a_R) / d.dx;
     d.Y0[p] = (1.0 - (1.0 - a_R) * std::sin(mb) / a_R) / d.dx;
-    d.phi0[p] = M_PI * (double)rows[p][0].nu / ((double)g.n_theta * g.m) - kHalo * d.dtheta;
+    d.phi0[p] = M_PI * (double)rows[p][0].nu / ((double)g.n_theta * g.m) - kHalo * d.dtheta_c;
   }
 
   // ---------------- host tables
@@ -404,7 +428,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   const double eps = 1e-9;  // samples within eps (in e^rho) of the boundary of D count as outside
   for (int p = 0; p < M; ++p) {
     for (int ti = 0; ti < NF; ++ti) {
-      const double phi = d.phi0[p] + (double)(d.t_min + ti) * (d.dtheta / r);
+      const double phi = d.phi0[p] + (double)(d.t_min + ti) * (d.dtheta_c / r);
       fine_cs[(size_t)p * NF + ti] = make_double2(std::cos(phi + p * d.beta), std::sin(phi + p * d.beta));
       // the ray of angle phi meets D (eq. circle_D) for e^rho in (c - root, c + root)
       const double disc = a_R * a_R - (1.0 - a_R) * (1.0 - a_R) * std::sin(phi) * std::sin(phi);
@@ -424,14 +448,14 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   }
   std::vector<float4> dec(r);
   {
-    auto dn = [&](int n) { return (std::abs(n) < 2 * r) ? bspline((double)n / r) / r : 0.0; };
+    auto dn = [&](int n) { return dec_tap(g.dec_filter, n, r); };
     for (int p = 0; p < r; ++p)
       dec[p] = make_float4((float)dn(p + r), (float)dn(p), (float)dn(p - r), (float)dn(p - 2 * r));
   }
   std::vector<float> dtap(4 * r - 1);
   for (int k = 0; k < 4 * r - 1; ++k) {
     const int nn = k - (2 * r - 1);
-    dtap[k] = (float)(bspline((double)nn / r) / r);
+    dtap[k] = (float)dec_tap(g.dec_filter, nn, r);
   }
   std::vector<int> own_j((size_t)M * n_own, -1);
   std::vector<double> own_cos((size_t)M * n_own, 1.0);
@@ -502,7 +526,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
 
   // ---------------- kernel table: zeta_hat on the device in FP64
   const int nkt = g.k_theta / 2 + 1, nkr = g.n_rho / 2 + 1;
-  const double P = g.k_theta * d.dtheta;
+  const double P = g.k_theta * d.dtheta_c;
   std::vector<double> xg, wg;
   gauss_legendre(16, xg, wg);
   const double max_rate = 2.0 * M_PI * (nkt - 1) / P + 2.0 * M_PI * (nkr - 1) / L * std::tan(d.beta);
@@ -592,7 +616,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
     for (int kt = 0; kt < nkt; ++kt) {
       double acc = 0.0;
       for (int n = -(2 * r - 1); n <= 2 * r - 1; ++n)
-        acc += bspline((double)n / r) / r * std::cos(2.0 * M_PI * kt * n / ((double)r * g.k_theta));
+        acc += dec_tap(g.dec_filter, n, r) * std::cos(2.0 * M_PI * kt * n / ((double)r * g.k_theta));
       dhat[kt] = acc;
     }
     const double norm = 1.0 / ((double)g.k_theta * g.n_rho);

@@ -35,8 +35,10 @@ inline Slices<T> dense(T* base, size_t stride) { return Slices<T>{base, nullptr,
 // Scalars and device tables handed to every kernel by value.
 struct DevPlan {
   int n, n_theta, n_s, m, n_rho, k_theta, r;
+  int q;                   // coarse lattice rows per sinogram row spacing (q_theta)
   int n_own, n_sup, n_fine, t_min, ld, nc, tw_len, lr;
   double a_R, dx, ds, dtheta, d_rho, rho0, beta;
+  double dtheta_c;         // coarse lattice spacing dtheta / q; fine rays dtheta_c / r apart
   double X0[kMaxPart], Y0[kMaxPart];   // image index of T_m^{-1}(0) offsets, per partition
   double phi0[kMaxPart];               // theta' of support row 0, per partition
   const float2* H;         // [nc + 1][k_theta/2 + 1], zeta_hat/(B_hat D_hat K N_rho)
@@ -118,9 +120,11 @@ rl_status launch_prefilter(const rl_plan* p, Slices<const float> in, Slices<floa
                            hipStream_t s);
 rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s);
 rl_status launch_rfft_rows(const rl_plan* p, const float* in, float2* out, int rows, hipStream_t s);
-// H: the multiplier table (nullptr: the plan's H of the Radon transform).
-rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int in_off, float2* out,
-                            int out_rows, int out_off, bool conj, int batch, hipStream_t s,
+// Input rows in_off + in_step * i (i < in_rows) and output rows out_off + out_step * o (o < out_rows)
+// of the K-row lattice; the other input rows are zero.  H: the multiplier table (nullptr: the
+// plan's H of the Radon transform).
+rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int in_off, int in_step, float2* out,
+                            int out_rows, int out_off, int out_step, bool conj, int batch, hipStream_t s,
                             const float2* H = nullptr);
 // scale: factor on the output (1 for R)
 rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, Slices<float> sino, int batch, double scale,

@@ -32,7 +32,8 @@ __global__ void k_tune_fill(float* x, size_t n) {
 bool tune_valid(const rl_tune& t) {
   return t.theta_cols >= 0 && t.theta_cols <= 8 && (t.theta_xcd_order == 0 || t.theta_xcd_order == 1) &&
          t.prefilter_rows >= 32 && t.prefilter_rows <= 4096 && t.prefilter_rows % 32 == 0 &&
-         (t.fwd_patch_split == 0 || t.fwd_patch_split == 1);
+         (t.fwd_patch_split == 0 || t.fwd_patch_split == 1) && (t.fwd_xcd_order == 0 || t.fwd_xcd_order == 1) &&
+         (t.adj_direct == 0 || t.adj_direct == 1);
 }
 
 std::string cache_key(const rl_plan* p, int batch) {
@@ -48,7 +49,7 @@ std::string cache_key(const rl_plan* p, int batch) {
   const rl_geom& g = p->g;
   std::ostringstream k;
   k << arch << " rocm=" << rt << " n=" << g.n << " n_theta=" << g.n_theta << " n_s=" << g.n_s << " m=" << g.m
-    << " n_rho=" << g.n_rho << " k_theta=" << g.k_theta << " r_dec=" << g.r_dec << " dec_filter=" << g.dec_filter
+    << " n_rho=" << g.n_rho << " k_theta=" << g.k_theta << " r_dec=" << g.r_dec << " dec_filter=" << g.dec_filter << " q_theta=" << g.q_theta
     << " batch=" << batch;
   return k.str();
 }
@@ -77,6 +78,7 @@ bool cache_lookup(const char* path, const std::string& key, rl_tune* out) {
     rl_tune t;
     if (json_int(line, "theta_cols", &t.theta_cols) && json_int(line, "theta_xcd_order", &t.theta_xcd_order) &&
         json_int(line, "prefilter_rows", &t.prefilter_rows) && json_int(line, "fwd_patch_split", &t.fwd_patch_split) &&
+        json_int(line, "fwd_xcd_order", &t.fwd_xcd_order) && json_int(line, "adj_direct", &t.adj_direct) &&
         tune_valid(t)) {
       *out = t;  // the last valid entry wins
       found = true;
@@ -90,8 +92,10 @@ bool cache_append(const char* path, const std::string& key, const rl_tune& t, fl
   if (!f) return false;
   const int n = std::fprintf(f,
                              "{\"key\": \"%s\", \"theta_cols\": %d, \"theta_xcd_order\": %d, \"prefilter_rows\": %d, "
-                             "\"fwd_patch_split\": %d, \"ms_fwd\": %.4f, \"ms_adj\": %.4f}\n",
-                             key.c_str(), t.theta_cols, t.theta_xcd_order, t.prefilter_rows, t.fwd_patch_split,
+                             "\"fwd_patch_split\": %d, \"fwd_xcd_order\": %d, \"adj_direct\": %d, \"ms_fwd\": %.4f, "
+                             "\"ms_adj\": %.4f}\n",
+                             key.c_str(), t.theta_cols, t.theta_xcd_order, t.prefilter_rows, t.fwd_patch_split, t.fwd_xcd_order,
+                             t.adj_direct,
                              ms_fwd, ms_adj);
   return std::fclose(f) == 0 && n > 0;
 }
@@ -203,11 +207,16 @@ extern "C" rl_status rl_plan_autotune(rl_plan* plan, int32_t batch, void* d_ws, 
   float best_f = 0.f, best_a = 0.f;
   st = run.time_both(&best_f, &best_a);
   // candidates of each field (coordinate descent); the objective is the sum of the R and R# times
-  const std::vector<std::vector<int>> cands = {{1, 2, 4, 8}, {0, 1}, {128, 256, 512, 1024}, {0, 1}};
+  const std::vector<std::vector<int>> cands = {{1, 2, 4, 8}, {0, 1}, {128, 256, 512, 1024}, {0, 1}, {0, 1}, {0, 1}};
   for (size_t f = 0; f < cands.size() && st == RL_OK; ++f) {
     for (int v : cands[f]) {
       rl_tune t = best;
-      int* field = f == 0 ? &t.theta_cols : f == 1 ? &t.theta_xcd_order : f == 2 ? &t.prefilter_rows : &t.fwd_patch_split;
+      int* field = f == 0   ? &t.theta_cols
+                   : f == 1 ? &t.theta_xcd_order
+                   : f == 2 ? &t.prefilter_rows
+                   : f == 3 ? &t.fwd_patch_split
+                   : f == 4 ? &t.fwd_xcd_order
+                            : &t.adj_direct;
       if (*field == v) continue;
       *field = v;
       plan->tune = t;

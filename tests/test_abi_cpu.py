@@ -44,20 +44,22 @@ def test_library_exports_every_declared_symbol(lib):
 @pytest.mark.parametrize("n,nt,ns", [(128, 180, 128), (1024, 1024, 1024), (2048, 2048, 2048), (2048, 1024, 2048),
                                      (256, 256, 256), (768, 768, 768), (64, 90, 64)])
 def test_defaults_match_oracle_geometry(lib, n, nt, ns):
-    g = _lib.geom_default(n, nt, ns, 4)
-    og = make_geometry(n, nt, ns)
-    assert (g.n_rho, g.k_theta, g.r_dec) == (og.n_rho, og.k_theta, og.r_dec)
+    for q in (1, 2):
+        g = _lib.geom_default(n, nt, ns, 4, q)
+        og = make_geometry(n, nt, ns, q_theta=q)
+        assert (g.n_rho, g.k_theta, g.r_dec, g.q_theta, g.dec_filter) == (og.n_rho, og.k_theta, og.r_dec, q, 0)
 
 
 def test_argument_errors_are_status_codes(lib):
     g = _lib.RlGeom()
-    assert lib.rl_geom_default(7, 10, 10, 4, ctypes.byref(g)) == 2
-    assert lib.rl_geom_default(64, 2, 64, 4, ctypes.byref(g)) == 2
-    assert lib.rl_geom_default(64, 64, 64, 4, None) == 1
+    assert lib.rl_geom_default(7, 10, 10, 4, 1, ctypes.byref(g)) == 2
+    assert lib.rl_geom_default(64, 2, 64, 4, 1, ctypes.byref(g)) == 2
+    assert lib.rl_geom_default(64, 64, 64, 4, 1, None) == 1
     p = ctypes.c_void_p()
     assert lib.rl_plan_create(None, ctypes.byref(p)) == 1
     good = _lib.geom_default(64, 90, 64)
-    for field, bad in (("n_rho", 96), ("n_rho", 64), ("k_theta", 16), ("r_dec", 1), ("m", 2), ("dec_filter", 3)):
+    for field, bad in (("n_rho", 96), ("n_rho", 64), ("k_theta", 16), ("r_dec", 1), ("m", 2), ("dec_filter", 3),
+                       ("q_theta", 3), ("q_theta", 0)):
         g = _lib.RlGeom.from_buffer_copy(good)
         setattr(g, field, bad)
         assert lib.rl_plan_create(ctypes.byref(g), ctypes.byref(p)) == 2, field

@@ -57,7 +57,8 @@ def get_plan(n, nt, ns, m=4, **kw):
     if key not in _plans:
         p = RadonPlan(n, nt, ns, m=m, **kw)
         g = p.geom
-        og = Geometry(g["n"], g["n_theta"], g["n_s"], g["m"], g["n_rho"], g["k_theta"], g["r_dec"]).validate()
+        og = Geometry(g["n"], g["n_theta"], g["n_s"], g["m"], g["n_rho"], g["k_theta"], g["r_dec"], g["dec_filter"],
+                      g["q_theta"]).validate()
         _plans[key] = (p, og)
     return _plans[key]
 
@@ -88,6 +89,48 @@ BIG_CASES = [
     (256, 4096, 256, 4, {}),
     (1024, 1024, 1024, 4, {}),
 ]
+
+
+# accuracy variants of Algorithm 1 step 4: the box low-pass (dec_filter 1), the coarse lattice at
+# half the sinogram's angular spacing (q_theta 2), and both; odd and even r, M = 3 and 5
+VARIANT_CASES = [
+    (128, 180, 128, 4, {"dec_filter": 1}),
+    (128, 180, 128, 4, {"q_theta": 2}),
+    (64, 90, 64, 4, {"dec_filter": 1, "q_theta": 2}),
+    (96, 97, 80, 5, {"q_theta": 2}),
+    (48, 100, 40, 3, {"dec_filter": 1}),
+    (256, 256, 256, 4, {"dec_filter": 1, "q_theta": 2}),
+]
+
+
+@pytest.mark.parametrize("case", VARIANT_CASES,
+                         ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}m{c[3]}" + "".join(f"-{k}{v}" for k, v in c[4].items()))
+def test_variant_parity(dev, case):
+    """R, R# and FBP on the step-4 variants against the oracle's reading of them."""
+    n, nt, ns, m, kw = case
+    plan, og = get_plan(n, nt, ns, m, **kw)
+    assert (og.dec_filter, og.q_theta) == (kw.get("dec_filter", 0), kw.get("q_theta", 1))
+    img, _ = inputs.ellipse_phantom(n, 8, 105)
+    img += 0.3 * inputs.uniform_image(n, 106)
+    got = plan.forward(to_dev(img, dev)).cpu().numpy()
+    check(f"R {case} r={og.r_dec} K={og.k_theta}", got, oradon.radon_fwd(og, f32(img)))
+    g = inputs.normal_array((nt, ns), 107)
+    got = plan.adjoint(to_dev(g, dev)).cpu().numpy()
+    check(f"R# {case}", got, oradon.radon_adj(og, f32(g)))
+    sino = oradon.radon_fwd(og, f32(img))
+    got = plan.fbp(to_dev(sino, dev)).cpu().numpy()
+    check(f"FBP {case}", got, oradon.fbp(og, f32(sino)))
+
+
+def test_bp_lp_rejects_half_spacing_lattice(dev):
+    """Algorithm 2 reads its lattice on the sinogram rows: q_theta = 2 is refused, not run."""
+    from paper_1506_00014_amd import _lib
+
+    plan, og = get_plan(64, 90, 64, 4, q_theta=2)
+    g = to_dev(inputs.normal_array((90, 64), 108), dev)
+    with pytest.raises(_lib.RadonLibError) as e:
+        plan.bp_lp(g)
+    assert e.value.status == _lib.RL_ERR_GEOMETRY
 
 
 # M = 5, 6, 8 (beta = pi/M) with rows at theta' = -beta/2 exactly, where the ray is tangent to D and
