@@ -679,7 +679,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int row = cg - 1 + i;
-          const bool ok = row >= 0 && row < P.n_sup;
+          const bool ok = row >= 0 && row < P.sup_rows[m];
           sw.dw[i] = ok ? dwv[i] * (1.0f / 36.0f) : 0.f;
           sw.roff[i] = (min(max(row, cg0), cg1) - cg0) * span;
         }

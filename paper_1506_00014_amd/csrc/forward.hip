@@ -343,7 +343,9 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __r
     float acc = 0.f;
     for (int k = 0; k < nd; ++k) acc += P.dtap[k] * vcol[k * kFQ];
     const float er = (float)(P.erho[q] * (P.a_R * P.dx));
-    u[((size_t)bm * P.n_sup + i) * P.n_rho + q] = acc * er;
+    // lattice rows past this partition's support (partitions own different numbers of rows) are
+    // zero: the theta convolution must not see the fine rays beyond its last halo row
+    u[((size_t)bm * P.n_sup + i) * P.n_rho + q] = i < P.sup_rows[m] ? acc * er : 0.f;
   }
 }
 

@@ -418,6 +418,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
     d.X0[p] = (1.0 - (1.0 - a_R) * std::cos(mb) / a_R) / d.dx;
     d.Y0[p] = (1.0 - (1.0 - a_R) * std::sin(mb) / a_R) / d.dx;
     d.phi0[p] = M_PI * (double)rows[p][0].nu / ((double)g.n_theta * g.m) - kHalo * d.dtheta_c;
+    d.sup_rows[p] = lattice_rows((int)rows[p].size(), g.q_theta) + 2 * kHalo;
   }
 
   // ---------------- host tables

@@ -41,6 +41,9 @@ struct DevPlan {
   double dtheta_c;         // coarse lattice spacing dtheta / q; fine rays dtheta_c / r apart
   double X0[kMaxPart], Y0[kMaxPart];   // image index of T_m^{-1}(0) offsets, per partition
   double phi0[kMaxPart];               // theta' of support row 0, per partition
+  int sup_rows[kMaxPart];              // support rows of each partition: the lattice rows of its own
+                                       // owned rows plus kHalo on each side (<= n_sup); the lattice
+                                       // rows beyond are zero in R and unread by its transpose
   const float2* H;         // [nc + 1][k_theta/2 + 1], zeta_hat/(B_hat D_hat K N_rho)
   const float2* Hbp;       // [nc + 1][k_theta/2 + 1], zeta#_hat/(B_hat_theta B_hat_rho K N_rho)
   const double2* fine_cs;  // [m][n_fine] (cos(phi_t + m beta), sin(phi_t + m beta))

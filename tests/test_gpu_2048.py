@@ -172,15 +172,13 @@ def test_gradient_finite_differences(setup):
     # (L(f + h v) - L(f - h v)) / 2h equals <grad L, v> for every h; the difference is
     # evaluated as sum((a - b)(a + b)) / 2h with a, b the residuals at f +- h v, avoiding the
     # cancellation of two sums of 4M squares.  With h = 1 the FP32 rounding of R(f +- h v) is
-    # small against a - b, so the bar is the parity bar.  With h = 1e-3 (the recipe's step)
-    # a - b = 2h R v is ~1e-3 of a and b, and each element of a - b carries the rounding of the
-    # two FP32 transforms, up to kappa u (|a| + |b|) with u = 2^-24 and kappa = 4 (the FP32
-    # chain's measured error against FP64 is ~2e-7 = 3.4 u relative); those errors are
-    # independent between elements, so the central difference's error has standard deviation
-    # about kappa u sqrt(sum (|a| + |b|)^2 (a + b)^2) / 2h; the bar is six of those (plus the
-    # parity bar).  Also checked: <grad L, v> against 2 <R v, R f - g>, which uses R on v directly.
-    u = 2.0 ** -24
-    kappa = 4.0
+    # small against a - b, so the bar is the parity bar.  With h = 1e-3 (the configuration's
+    # step) a - b = 2h R v is ~1e-3 of a and b, so the central difference mostly measures how
+    # differently the two FP32 transforms round: f + h v and f - h v round almost alike (their
+    # rounding largely cancels in a - b), so the difference stays near 1e-2 of <grad L, v>, but no
+    # useful bound follows from the FP32 chain's elementwise error (that bound is above 1).  The
+    # h = 1e-3 check is therefore a sanity bar of 5e-2; the exact gradient is pinned by h = 1,
+    # by 2 <R v, R f - g> (R on v directly) and by the oracle gradient at 128^2.
     worst = {1.0: 0.0, 1e-3: 0.0}
     r0 = resid(f0)
     for k in range(16):
@@ -194,8 +192,7 @@ def test_gradient_finite_differences(setup):
         for h in (1.0, 1e-3):
             a, b = resid(f0 + h * v), resid(f0 - h * v)
             fd = ((a - b) * (a + b)).sum().item() / (2 * h)
-            sd = kappa * u * (((a.abs() + b.abs()) * (a + b)) ** 2).sum().sqrt().item() / (2 * h)
-            bar = TOL + 6.0 * sd / abs(an)
+            bar = TOL if h == 1.0 else 5e-2
             rel = abs(fd - an) / abs(an)
             line += f"  h={h:g}: fd {fd:.6e} rel {rel:.1e} (bar {bar:.1e})"
             assert rel <= bar, (k, h, rel, bar)
