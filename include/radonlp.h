@@ -224,6 +224,24 @@ rl_status radon_transpose(const rl_plan* plan, const float* d_sino, float* d_img
 rl_status radon_adj_transpose(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch,
                               void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* Bytes of the static device scratch that radon_fwd_noalloc uses as its workspace (128 MiB:
+ * one 2048 x 2048 slice at the default geometry needs about 118 MB). */
+#define RL_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): radon_fwd with its workspace in a file-scope device array of
+ * RL_NOALLOC_SCRATCH_BYTES bytes instead of a caller-provided buffer.  Same arguments (minus the
+ * workspace), layouts, results (the same kernels: bitwise equal to radon_fwd), asynchrony and
+ * errors as radon_fwd; it calls no hipMalloc / hipFree.  Each GPU holds one copy of the array,
+ * from the library's load on that GPU until the process ends; its device address is looked up
+ * once per GPU on the first call there.  RL_ERR_WORKSPACE if rl_workspace_bytes(plan, batch,
+ * RL_OP_FWD) exceeds RL_NOALLOC_SCRATCH_BYTES.  All calls on one GPU share that GPU's copy:
+ * calls that overlap in time on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller; calls in order on one stream are safe.  d_img and d_sino are
+ * caller-owned device memory as for radon_fwd. */
+rl_status radon_fwd_noalloc(const rl_plan* plan, const float* d_img, float* d_sino, int32_t batch,
+                            hipStream_t stream);
+
 /* Filtered back-projection f = R# W g (sec. 1 eq. FBP): W is the filter of sec. 6 chosen by
  * `filter`, applied along s: the ramp |sigma| (eq. ramp) as a linear (zero-padded)
  * convolution with the Ram-Lak kernel h_0 = 1/(4 ds^2), h_n = -1/(pi^2 n^2 ds^2) for odd n,

@@ -27,6 +27,7 @@ RL_FILTER_RAMLAK = 0
 RL_FILTER_COSINE = 1
 RL_FILTER_SHEPP_LOGAN = 2
 FILTERS = {"ramlak": RL_FILTER_RAMLAK, "cosine": RL_FILTER_COSINE, "shepp-logan": RL_FILTER_SHEPP_LOGAN}
+NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024  # RL_NOALLOC_SCRATCH_BYTES
 RL_STAGE_PREFILTER, RL_STAGE_LOGPOLAR, RL_STAGE_CONV, RL_STAGE_KERNEL = 0, 1, 2, 3
 
 # Every function declared in include/radonlp.h.
@@ -46,6 +47,7 @@ EXPORTED = (
     "radon_adj",
     "radon_transpose",
     "radon_adj_transpose",
+    "radon_fwd_noalloc",
     "fbp",
     "radon_bp_lp",
     "fbp_lp",
@@ -143,6 +145,8 @@ def load(path: str = LIB_PATH):
         f = getattr(lib, name)
         f.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]
         f.restype = c_int32
+    lib.radon_fwd_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
+    lib.radon_fwd_noalloc.restype = c_int32
     for name in ("fbp", "fbp_lp"):
         f = getattr(lib, name)
         f.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_size_t, c_void_p]

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libradonlp.so")
-SOURCES = ["plan.hip", "forward.hip", "adjoint.hip", "bp.hip", "batch.hip", "em.hip", "tune.hip"]
+SOURCES = ["plan.hip", "forward.hip", "adjoint.hip", "bp.hip", "batch.hip", "em.hip", "tune.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
