@@ -122,10 +122,11 @@ typedef struct rl_plan rl_plan;
  *   fwd_xcd_order    1: blocks of the forward gather are ordered so that each XCD (with its own
  *                    L2) runs one contiguous run of the tile list (neighbouring tiles read
  *                    overlapping image boxes); 0: launch order
- *   adj_direct       1: the back-projection's Cartesian splat adds every sample's 16 weighted
- *                    values to its LDS tile directly; 0: it sums them in a register footprint that
- *                    follows the ray and adds only what the footprint leaves behind.  The two
- *                    add the same FP32 terms in FP64 in a different order.
+ *   adj_walk         walk of the back-projection's Cartesian splat (both sum each sample's 16
+ *                    weighted values in a register footprint that follows the ray and add what it
+ *                    leaves behind to the LDS tile): 0 moves the footprint under branches, 1 moves
+ *                    it by selects every step (uniform across a wave).  The two add the same FP32
+ *                    terms in FP64 in a different order.
  * Defaults (rl_plan_create): 0, 1, 512, 1, 1, 0. */
 typedef struct {
   int32_t theta_cols;
@@ -133,7 +134,7 @@ typedef struct {
   int32_t prefilter_rows;
   int32_t fwd_patch_split;
   int32_t fwd_xcd_order;
-  int32_t adj_direct;
+  int32_t adj_walk;
 } rl_tune;
 
 /* Read / replace the plan's launch parameters.  rl_plan_set_tuning validates *tune

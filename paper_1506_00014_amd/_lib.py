@@ -91,7 +91,7 @@ class RlTune(ctypes.Structure):
         ("prefilter_rows", ctypes.c_int32),
         ("fwd_patch_split", ctypes.c_int32),
         ("fwd_xcd_order", ctypes.c_int32),
-        ("adj_direct", ctypes.c_int32),
+        ("adj_walk", ctypes.c_int32),
     ]
 
     def as_dict(self):

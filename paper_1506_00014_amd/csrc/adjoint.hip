@@ -285,33 +285,143 @@ __device__ __forceinline__ void splat_walk(const SegWalk& sw, double* acc, const
   }
 }
 
-// Walk one segment without a register footprint: each sample is rebuilt as in splat_walk and
-// its 16 weighted values go straight to the FP64 LDS tile.  Every lane runs the same
-// instructions at every sample (no footprint moves), at the price of 16 LDS atomics per sample.
-__device__ __forceinline__ void splat_walk_direct(const SegWalk& sw, double* acc, const float* rows,
-                                                  const double* erho, int qlo) {
-  // LDS index of pixel (x, y), unwrapped index coordinates: (y - uy0 + kAHalo) kAP + x - ux0 + kAHalo
-  const int obase = (kAHalo - 1 - sw.uy0) * kAP + (kAHalo - 1 - sw.ux0);
-  for (int q = sw.qbeg; q <= sw.qend; ++q) {
-    const int qi = q - qlo;
-    const double E = erho[qi];
-    // (dw carries the weights' 1/36)
-    const float V = sw.dw[0] * rows[sw.roff[0] + qi] + sw.dw[1] * rows[sw.roff[1] + qi] +
-                    sw.dw[2] * rows[sw.roff[2] + qi] + sw.dw[3] * rows[sw.roff[3] + qi];
+// The same walk with the footprint moves made uniform across a wave.  Coordinates are mirrored
+// so that every ray runs towards +x and +y (X' = sx X, Y' = sy Y with sx, sy the signs of the
+// ray direction; B is even, so the mirrored taps carry the same weights): the footprint then
+// only ever drops its column i = 0 or its row j = 0.  Each step every lane shifts its
+// registers by selects (a move of 0 keeps them), and only the flush of the dropped column or
+// row (four FP64 LDS atomics) sits under a branch, so the registers need no copies at the
+// branches' joins.  The coarse rows come from the interleaved copy: the four rows of the ray
+// at rho index q are consecutive.
+struct SegWalk2 {
+  double X0, Y0;           // x* in mirrored image-index coordinates (sx X0, sy Y0)
+  double cx, cy;           // |ray direction|
+  int qbeg, qend;          // rho indices of the segment (inclusive)
+  int lox, hix, loy, hiy;  // range of the footprint origin (mirrored), as in splat_walk
+  int cstep, rstep;        // LDS index steps of one mirrored column (sx) and row (sy kAP)
+  int obase;               // LDS index of mirrored pixel (c, r) is obase + sx c + sy kAP r
+  float dw[4];             // decimation weights (with the bicubic weights' 1/36)
+  int rrow;                // offset of the ray's first coarse row in an interleaved rho step
+};
+
+// One row of the register footprint (named members, so that the moves below stay selects on
+// registers and never become indexed loads from a private array).
+struct Row4 {
+  float c0, c1, c2, c3;
+};
+
+// b where lane mask m has this lane's bit, else a: one v_cndmask_b32.  Written as an
+// instruction so that the compiler keeps it a select instead of merging it into the branch
+// on the same condition (which brings back register copies at the branch's join).
+__device__ __forceinline__ float lane_select(float a, float b, unsigned long long m) {
+  float r;
+  asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(m));
+  return r;
+}
+
+__device__ __forceinline__ void splat_walk_bf(const SegWalk2& sw, double* acc, const float* rows, int rstride,
+                                              const double* erho, int qlo) {
+  if (sw.qend < sw.qbeg) return;
+  const int cs = sw.cstep, rs = sw.rstep;
+  Row4 r0 = {0.f, 0.f, 0.f, 0.f}, r1 = r0, r2 = r0, r3 = r0;
+  int ckx, cky;
+  {
+    const double E = erho[sw.qbeg - qlo];
+    const double X = sw.X0 + E * sw.cx, Y = sw.Y0 + E * sw.cy;
+    ckx = min(max((int)floor(X), sw.lox), sw.hix);
+    cky = min(max((int)floor(Y), sw.loy), sw.hiy);
+  }
+  const float* rp = rows + (sw.qbeg - qlo) * rstride + sw.rrow;
+  for (int q = sw.qbeg; q <= sw.qend; ++q, rp += rstride) {
+    const double E = erho[q - qlo];
+    const float V = sw.dw[0] * rp[0] + sw.dw[1] * rp[1] + sw.dw[2] * rp[2] + sw.dw[3] * rp[3];
     const double X = sw.X0 + E * sw.cx, Y = sw.Y0 + E * sw.cy;
     const double fx = floor(X), fy = floor(Y);
-    // as in splat_walk, the clamp only keeps the adds inside the halo
-    const int kx = min(max((int)fx, sw.ux0 - 3), sw.ux1 + 1), ky = min(max((int)fy, sw.uy0 - 3), sw.uy1 + 1);
+    const int kx = min(max((int)fx, sw.lox), sw.hix);
+    const int ky = min(max((int)fy, sw.loy), sw.hiy);
+    // a step moves the origin by at most one pixel per axis forward (samples are less than a
+    // pixel apart along a ray); anything else (only the clamp could cause it) flushes all
+    if (((unsigned)(kx - ckx) | (unsigned)(ky - cky)) > 1u) {
+      const int o = sw.obase + cs * (ckx - 1) + rs * (cky - 1);
+      const Row4* rr[4] = {&r0, &r1, &r2, &r3};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        atomicAdd(acc + o + j * rs, (double)rr[j]->c0);
+        atomicAdd(acc + o + j * rs + cs, (double)rr[j]->c1);
+        atomicAdd(acc + o + j * rs + 2 * cs, (double)rr[j]->c2);
+        atomicAdd(acc + o + j * rs + 3 * cs, (double)rr[j]->c3);
+      }
+      r0 = Row4{0.f, 0.f, 0.f, 0.f};
+      r1 = r0;
+      r2 = r0;
+      r3 = r0;
+      ckx = kx;
+      cky = ky;
+    }
+    const bool mx = kx != ckx, my = ky != cky;
+    if (mx) {  // drop column 0
+      const int o = sw.obase + cs * (ckx - 1) + rs * (cky - 1);
+      atomicAdd(acc + o, (double)r0.c0);
+      atomicAdd(acc + o + rs, (double)r1.c0);
+      atomicAdd(acc + o + 2 * rs, (double)r2.c0);
+      atomicAdd(acc + o + 3 * rs, (double)r3.c0);
+    }
+    const unsigned long long bx = __builtin_amdgcn_ballot_w64(mx), by = __builtin_amdgcn_ballot_w64(my);
+    const float zero = 0.f;
+#define RL_SHIFT_X(r)                   \
+  r.c0 = lane_select(r.c0, r.c1, bx);   \
+  r.c1 = lane_select(r.c1, r.c2, bx);   \
+  r.c2 = lane_select(r.c2, r.c3, bx);   \
+  r.c3 = lane_select(r.c3, zero, bx);
+    RL_SHIFT_X(r0)
+    RL_SHIFT_X(r1)
+    RL_SHIFT_X(r2)
+    RL_SHIFT_X(r3)
+#undef RL_SHIFT_X
+    if (my) {  // drop row 0
+      const int o = sw.obase + cs * (kx - 1) + rs * (cky - 1);
+      atomicAdd(acc + o, (double)r0.c0);
+      atomicAdd(acc + o + cs, (double)r0.c1);
+      atomicAdd(acc + o + 2 * cs, (double)r0.c2);
+      atomicAdd(acc + o + 3 * cs, (double)r0.c3);
+    }
+#define RL_SHIFT_Y(c)                   \
+  r0.c = lane_select(r0.c, r1.c, by);   \
+  r1.c = lane_select(r1.c, r2.c, by);   \
+  r2.c = lane_select(r2.c, r3.c, by);   \
+  r3.c = lane_select(r3.c, zero, by);
+    RL_SHIFT_Y(c0)
+    RL_SHIFT_Y(c1)
+    RL_SHIFT_Y(c2)
+    RL_SHIFT_Y(c3)
+#undef RL_SHIFT_Y
+    ckx = kx;
+    cky = ky;
     float wx[4], wy[4];
     bspline_w6((float)(X - fx), wx);
     bspline_w6((float)(Y - fy), wy);
-    double* a = acc + obase + ky * kAP + kx;  // pixel (kx - 1, ky - 1)
+#define RL_ACC(r, j)                         \
+  {                                          \
+    const float vy = V * wy[j];              \
+    r.c0 = fmaf(vy, wx[0], r.c0);            \
+    r.c1 = fmaf(vy, wx[1], r.c1);            \
+    r.c2 = fmaf(vy, wx[2], r.c2);            \
+    r.c3 = fmaf(vy, wx[3], r.c3);            \
+  }
+    RL_ACC(r0, 0)
+    RL_ACC(r1, 1)
+    RL_ACC(r2, 2)
+    RL_ACC(r3, 3)
+#undef RL_ACC
+  }
+  const int o = sw.obase + cs * (ckx - 1) + rs * (cky - 1);
+  const Row4 rr[4] = {r0, r1, r2, r3};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float vy = V * wy[j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) atomicAdd(a + j * kAP + i, (double)(vy * wx[i]));
-    }
+  for (int j = 0; j < 4; ++j) {
+    atomicAdd(acc + o + j * rs, (double)rr[j].c0);
+    atomicAdd(acc + o + j * rs + cs, (double)rr[j].c1);
+    atomicAdd(acc + o + j * rs + 2 * cs, (double)rr[j].c2);
+    atomicAdd(acc + o + j * rs + 3 * cs, (double)rr[j].c3);
   }
 }
 
@@ -559,7 +669,7 @@ rl_status build_adj_passes(rl_plan* p) {
 // of its rays are copied to LDS with e^rho for one window of rho indices at a time (one
 // window usually covers the pass), and every thread walks at most one segment.  The FP64
 // tile (with its halo) collects all partitions and is written once.
-template <bool DIRECT>
+template <bool BF>
 __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const float* __restrict__ U,
                                                               float* __restrict__ cbar) {
   // FP64: LDS float atomics are slow on this target.
@@ -608,15 +718,38 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
       rppre[nslot] = total - nfull;
     }
     // rho windows of the row copies; a window starts at a multiple of 4 and spans a multiple
-    // of 4, so rows are copied as float4 (n_rho is a power of two)
-    const int nur = cg1 - cg0 + 1;
+    // of 4, so rows are copied as float4 (n_rho is a power of two).  The branch-free walk
+    // reads an interleaved copy [rho][row] of the rows rlo .. rhi, which covers every ray's rows
+    // cg - 1 .. cg + 2 (the pass header clamps cg0, cg1 to the support; where it did, the copy
+    // reaches three rows below 0 or four above the last lattice row), rows outside the
+    // partition's support copied as zeros
+    const int rlo = BF ? (cg0 == 0 ? -3 : cg0) : cg0;
+    const int rhi = BF ? (cg1 == P.n_sup - 1 ? P.n_sup + 3 : cg1) : cg1;
+    const int nur = rhi - rlo + 1;
     const int wlen = max(4, (min(kECap, kUCap / nur) - 4) & ~3);  // nur <= kARows + 3, so >= 32
     for (int wq = qlo; wq <= qhi; wq += wlen) {
       const int wq4 = wq & ~3;
       const int wend = min(wq + wlen - 1, qhi);  // last rho index walked in this window
       const int span = (wend - wq4 + 4) & ~3;    // copied: [wq4, wq4 + span)
       if (wq > qlo) __syncthreads();  // the previous window's walk is done with the copies
-      {
+      if (BF) {
+        // group i: rho group g = i / nur, row rr = i % nur (consecutive threads, consecutive rows)
+        const int sg = span >> 2, tot = nur * sg;
+        const int srows = P.sup_rows[m];
+        for (int i = threadIdx.x; i < tot; i += kAThreads) {
+          const int g = i / nur, rr = i - g * nur;
+          const int row = rlo + rr;
+          const float4 v = (row >= 0 && row < srows)
+                               ? *reinterpret_cast<const float4*>(Ub + (size_t)row * P.n_rho + wq4 + 4 * g)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+          float* d = us + 4 * g * nur + rr;
+          d[0] = v.x;
+          d[nur] = v.y;
+          d[2 * nur] = v.z;
+          d[3 * nur] = v.w;
+        }
+        if (threadIdx.x < span) es[threadIdx.x] = P.erho[wq4 + threadIdx.x];
+      } else {
         constexpr int kIt = (kUCap / 4 + kAThreads - 1) / kAThreads;
         const int sg = span >> 2, tot = nur * sg;
         // group i = threadIdx.x + it * kAThreads is (row, g) = divmod(i, sg); both advance by
@@ -658,13 +791,41 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
           else hi = mid - 1;
         }
         const int k = lo;
+        const int q0 = rq0[k] + (full ? j - rpre[k] : rpre[k + 1] - rpre[k]) * seglen;
+        if (BF) {
+          SegWalk2 sw;
+          const double2 tcs = rcs[k];
+          const bool xp = tcs.x >= 0.0, yp = tcs.y >= 0.0;
+          sw.X0 = xp ? X0 : -X0;
+          sw.Y0 = yp ? Y0 : -Y0;
+          sw.cx = fabs(tcs.x);
+          sw.cy = fabs(tcs.y);
+          sw.qbeg = max(q0, wq);
+          sw.qend = min(min(q0 + seglen - 1, rcnt[k]), wend);
+          // footprint origins kx in [ux0 - 3, ux1 + 1] (columns kx - 1 .. kx + 2); mirrored,
+          // the columns -kx' + 1 .. -kx' - 2 give kx' in [-ux1 - 2, -ux0 + 2]
+          sw.lox = xp ? ux0 - 3 : -ux1 - 2;
+          sw.hix = xp ? ux1 + 1 : -ux0 + 2;
+          sw.loy = yp ? uy0 - 3 : -uy1 - 2;
+          sw.hiy = yp ? uy1 + 1 : -uy0 + 2;
+          sw.cstep = xp ? 1 : -1;
+          sw.rstep = yp ? kAP : -kAP;
+          sw.obase = (kAHalo - uy0) * kAP + (kAHalo - ux0);
+          const float4 dw = rdw[k];
+          sw.dw[0] = dw.x * (1.0f / 36.0f);
+          sw.dw[1] = dw.y * (1.0f / 36.0f);
+          sw.dw[2] = dw.z * (1.0f / 36.0f);
+          sw.dw[3] = dw.w * (1.0f / 36.0f);
+          sw.rrow = rcg[k] - 1 - rlo;
+          splat_walk_bf(sw, acc, us, nur, es, wq4);
+          continue;
+        }
         SegWalk sw;
         sw.X0 = X0;
         sw.Y0 = Y0;
         const double2 tcs = rcs[k];
         sw.cx = tcs.x;
         sw.cy = tcs.y;
-        const int q0 = rq0[k] + (full ? j - rpre[k] : rpre[k + 1] - rpre[k]) * seglen;
         sw.qbeg = max(q0, wq);
         sw.qend = min(min(q0 + seglen - 1, rcnt[k]), wend);
         sw.ux0 = ux0;
@@ -683,8 +844,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
           sw.dw[i] = ok ? dwv[i] * (1.0f / 36.0f) : 0.f;
           sw.roff[i] = (min(max(row, cg0), cg1) - cg0) * span;
         }
-        if (DIRECT) splat_walk_direct(sw, acc, us, es, wq4);
-        else splat_walk(sw, acc, us, es, wq4);
+        splat_walk(sw, acc, us, es, wq4);
       }
     }
   }
@@ -700,7 +860,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
 rl_status launch_lp2cart_adj(const rl_plan* p, const float* U, float* cbar, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   dim3 grid((d.n + kTile - 1) / kTile, (d.n + kTile - 1) / kTile, batch);
-  if (p->tune.adj_direct)
+  if (p->tune.adj_walk)
     RL_LAUNCH("k_lp2cart_adj", k_lp2cart_adj<true>, grid, dim3(kAThreads), 0, s, d, U, cbar);
   else
     RL_LAUNCH("k_lp2cart_adj", k_lp2cart_adj<false>, grid, dim3(kAThreads), 0, s, d, U, cbar);

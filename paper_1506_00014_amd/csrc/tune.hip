@@ -33,7 +33,7 @@ bool tune_valid(const rl_tune& t) {
   return t.theta_cols >= 0 && t.theta_cols <= 8 && (t.theta_xcd_order == 0 || t.theta_xcd_order == 1) &&
          t.prefilter_rows >= 32 && t.prefilter_rows <= 4096 && t.prefilter_rows % 32 == 0 &&
          (t.fwd_patch_split == 0 || t.fwd_patch_split == 1) && (t.fwd_xcd_order == 0 || t.fwd_xcd_order == 1) &&
-         (t.adj_direct == 0 || t.adj_direct == 1);
+         (t.adj_walk == 0 || t.adj_walk == 1);
 }
 
 std::string cache_key(const rl_plan* p, int batch) {
@@ -78,7 +78,7 @@ bool cache_lookup(const char* path, const std::string& key, rl_tune* out) {
     rl_tune t;
     if (json_int(line, "theta_cols", &t.theta_cols) && json_int(line, "theta_xcd_order", &t.theta_xcd_order) &&
         json_int(line, "prefilter_rows", &t.prefilter_rows) && json_int(line, "fwd_patch_split", &t.fwd_patch_split) &&
-        json_int(line, "fwd_xcd_order", &t.fwd_xcd_order) && json_int(line, "adj_direct", &t.adj_direct) &&
+        json_int(line, "fwd_xcd_order", &t.fwd_xcd_order) && json_int(line, "adj_walk", &t.adj_walk) &&
         tune_valid(t)) {
       *out = t;  // the last valid entry wins
       found = true;
@@ -92,10 +92,10 @@ bool cache_append(const char* path, const std::string& key, const rl_tune& t, fl
   if (!f) return false;
   const int n = std::fprintf(f,
                              "{\"key\": \"%s\", \"theta_cols\": %d, \"theta_xcd_order\": %d, \"prefilter_rows\": %d, "
-                             "\"fwd_patch_split\": %d, \"fwd_xcd_order\": %d, \"adj_direct\": %d, \"ms_fwd\": %.4f, "
+                             "\"fwd_patch_split\": %d, \"fwd_xcd_order\": %d, \"adj_walk\": %d, \"ms_fwd\": %.4f, "
                              "\"ms_adj\": %.4f}\n",
                              key.c_str(), t.theta_cols, t.theta_xcd_order, t.prefilter_rows, t.fwd_patch_split, t.fwd_xcd_order,
-                             t.adj_direct,
+                             t.adj_walk,
                              ms_fwd, ms_adj);
   return std::fclose(f) == 0 && n > 0;
 }
@@ -216,7 +216,7 @@ extern "C" rl_status rl_plan_autotune(rl_plan* plan, int32_t batch, void* d_ws, 
                    : f == 2 ? &t.prefilter_rows
                    : f == 3 ? &t.fwd_patch_split
                    : f == 4 ? &t.fwd_xcd_order
-                            : &t.adj_direct;
+                            : &t.adj_walk;
       if (*field == v) continue;
       *field = v;
       plan->tune = t;

@@ -131,7 +131,7 @@ def test_tuning_does_not_change_results(setup):
     r0, b0 = plan.forward(x), plan.adjoint(y)
     try:
         for field, values in (("theta_cols", (1, 2, 3, 8)), ("theta_xcd_order", (0,)), ("prefilter_rows", (32, 96, 1024)),
-                              ("fwd_patch_split", (0,)), ("fwd_xcd_order", (0, 1)), ("adj_direct", (1,))):
+                              ("fwd_patch_split", (0,)), ("fwd_xcd_order", (0, 1)), ("adj_walk", (0, 1))):
             for v in values:
                 plan.tuning = {**default, field: v}
                 assert torch.equal(plan.forward(x), r0), (field, v)
