@@ -290,8 +290,9 @@ def em_detail(plan, f, sino, B, reps, time_op, detail, log):
 
 
 def m_sweep_detail(n, time_op, log, batch=16, seed=405):
-    """R and R# on `batch` slices of n x n (n angles x n bins) for M = 3, 4, 6, 8 partitions:
-    M sets the other geometry fields (N_rho, K, r) through rl_geom_default."""
+    """R and R# on `batch` slices of n x n (n angles x n bins) for M = 3, 4, 6, 8 partitions, with
+    the FFT lengths at the smallest powers of two meeting their bounds and at the smallest 2^a 3^b
+    (rl_geom_default's two policies; M sets N_rho, K and r)."""
     import torch
     from paper_1506_00014_amd import RadonPlan, _lib
 
@@ -299,18 +300,20 @@ def m_sweep_detail(n, time_op, log, batch=16, seed=405):
     f = torch.rand(batch, n, n, device="cuda", generator=gen)
     out = {}
     for m in (3, 4, 6, 8):
-        plan = RadonPlan(n, n, n, m=m)
-        ws = torch.empty(max(plan.workspace_bytes(batch, op) for op in (_lib.RL_OP_FWD, _lib.RL_OP_ADJ)),
-                         dtype=torch.uint8, device="cuda")
-        g = plan.forward(f, ws)
-        tf = time_op(lambda: plan.forward(f, ws), 3)
-        ta = time_op(lambda: plan.adjoint(g, ws), 3)
-        geo = plan.geom
-        out[str(m)] = {"n_rho": geo["n_rho"], "k_theta": geo["k_theta"], "r_dec": geo["r_dec"],
-                       "R_slices_per_s": round(batch / (tf / 1000.0), 1),
-                       "R#_slices_per_s": round(batch / (ta / 1000.0), 1)}
-        log(f"M={m}: {out[str(m)]}")
-        del plan, ws, g
+        for smooth in (False, True):
+            plan = RadonPlan(n, n, n, m=m, smooth=smooth)
+            ws = torch.empty(max(plan.workspace_bytes(batch, op) for op in (_lib.RL_OP_FWD, _lib.RL_OP_ADJ)),
+                             dtype=torch.uint8, device="cuda")
+            g = plan.forward(f, ws)
+            tf = time_op(lambda: plan.forward(f, ws), 3)
+            ta = time_op(lambda: plan.adjoint(g, ws), 3)
+            geo = plan.geom
+            key = f"{m}" + (" 2^a3^b" if smooth else "")
+            out[key] = {"n_rho": geo["n_rho"], "k_theta": geo["k_theta"], "r_dec": geo["r_dec"],
+                        "R_slices_per_s": round(batch / (tf / 1000.0), 1),
+                        "R#_slices_per_s": round(batch / (ta / 1000.0), 1)}
+            log(f"M={key}: {out[key]}")
+            del plan, ws, g
     return out
 
 
@@ -464,6 +467,8 @@ def main():
     ap.add_argument("--no-c5", action="store_true", help="skip the batched least-squares reconstruction")
     ap.add_argument("--no-em", action="store_true",
                     help="skip the EM step measurement (its normalisation is a batch-1 back-projection)")
+    ap.add_argument("--tune", action="append", default=[], metavar="FIELD=VALUE",
+                    help="set an execution-only launch parameter of the 2048^2 plan (rl_tune field), e.g. adj_walk=1")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (FETCH_SIZE / WRITE_SIZE calibration)")
     args = ap.parse_args()
@@ -486,6 +491,8 @@ def main():
     n = args.n
     B = args.batch
     plan = RadonPlan(n, n, n)
+    if args.tune:
+        plan.tuning = {kv.split("=", 1)[0]: int(kv.split("=", 1)[1]) for kv in args.tune}
     g = plan.geom
     n_own = plan.n_own()
     gen = torch.Generator(device=dev)
@@ -499,7 +506,7 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    log(f"plan {g}, batch {B}, workspace {ws_bytes / 2**30:.2f} GiB")
+    log(f"plan {g}, batch {B}, workspace {ws_bytes / 2**30:.2f} GiB, launch parameters {plan.tuning}")
 
     def step():
         sino = plan.forward(f, ws)
@@ -629,7 +636,8 @@ def main():
         "config": {"workload": f"R, R# and FBP (ramp) on a batch of {B} slices of {n}x{n}, "
                                f"{g['n_theta']} angles x {g['n_s']} bins, f ~ U[0,1]",
                    "n": n, "n_theta": g["n_theta"], "n_s": g["n_s"], "batch": B, "m": g["m"],
-                   "n_rho": g["n_rho"], "k_theta": g["k_theta"], "r_dec": g["r_dec"]},
+                   "n_rho": g["n_rho"], "k_theta": g["k_theta"], "r_dec": g["r_dec"],
+                   "launch_parameters": plan.tuning},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -77,11 +77,12 @@ typedef enum { RL_FILTER_RAMLAK = 0, RL_FILTER_COSINE = 1, RL_FILTER_SHEPP_LOGAN
  *   n_theta  angles N_theta >= m, <= 16384
  *   n_s      detector bins N_s, 2 <= N_s <= 4096
  *   m        angular partitions M >= 3, beta = pi/M (sec. 2)
- *   n_rho    rho-FFT length, a power of two >= ceil(log a_r / log(1 - 2 a_R / N))
+ *   n_rho    rho-FFT length 2^a 3^b, a multiple of 4, >= ceil(log a_r / log(1 - 2 a_R / N))
  *            (sec. 3 eq. vrho), <= 8192
- *   k_theta  theta-FFT length, a power of two >= 2*q_theta*ceil(N_theta/M) (sec. 5, the
- *            grid of size 2 N_theta / M, in lattice rows), >= n_sup = q_theta*(n_own - 1) + 5
- *            (the lattice rows of the owned rows plus two on each side), <= 2048
+ *   k_theta  theta-FFT length >= 2*q_theta*ceil(N_theta/M) (sec. 5, the grid of size
+ *            2 N_theta / M, in lattice rows), >= n_sup = q_theta*(n_own - 1) + 5 (the lattice
+ *            rows of the owned rows plus two on each side): 8, 12, 16, 24, 32, or 32 times one
+ *            of 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64 (the theta pass's four-step splits)
  *   r_dec    fine angular oversampling of the log-polar grid: (Delta theta / q_theta) / r_dec
  *            <= 2 a_R / N (sec. 3, before eq. Lopolargrid_f), <= 32
  *   dec_filter  theta low-pass used to go from the fine grid to the coarse one
@@ -160,11 +161,13 @@ rl_status rl_plan_autotune(rl_plan* plan, int32_t batch, void* d_ws, size_t ws_b
                            const char* cache_path);
 
 /* Fill *out with the default geometry for (n, n_theta, n_s, m) on a coarse lattice q_theta (1 or
- * 2) times finer than the sinogram rows: n_rho and k_theta are the smallest powers of two
- * meeting their bounds, r_dec the smallest integer meeting its bound, dec_filter = 0.
- * Host-only; touches no device.  Returns RL_ERR_GEOMETRY if no valid geometry exists within the
- * limits above. */
-rl_status rl_geom_default(int32_t n, int32_t n_theta, int32_t n_s, int32_t m, int32_t q_theta, rl_geom* out);
+ * 2) times finer than the sinogram rows: n_rho and k_theta are the smallest lengths meeting
+ * their bounds among the powers of two (smooth = 0) or among the lengths 2^a 3^b the FFTs take
+ * (smooth = 1; see n_rho and k_theta above), r_dec the smallest integer meeting its bound,
+ * dec_filter = 0.  Host-only; touches no device.  Returns RL_ERR_GEOMETRY if no valid geometry
+ * exists within the limits above. */
+rl_status rl_geom_default(int32_t n, int32_t n_theta, int32_t n_s, int32_t m, int32_t q_theta, int32_t smooth,
+                          rl_geom* out);
 
 /* Validate *geom and build a plan on the current device: partition tables, masks, the
  * Fourier multiplier H = zeta_hat / (B_hat_rho D_hat_theta) of sec. 3 eq. (exprcoef1)

@@ -119,7 +119,7 @@ def load(path: str = LIB_PATH):
         )
     lib = ctypes.CDLL(path)
     c_int32, c_size_t, c_void_p = ctypes.c_int32, ctypes.c_size_t, ctypes.c_void_p
-    lib.rl_geom_default.argtypes = [c_int32, c_int32, c_int32, c_int32, c_int32, ctypes.POINTER(RlGeom)]
+    lib.rl_geom_default.argtypes = [c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, ctypes.POINTER(RlGeom)]
     lib.rl_geom_default.restype = c_int32
     lib.rl_plan_create.argtypes = [ctypes.POINTER(RlGeom), ctypes.POINTER(c_void_p)]
     lib.rl_plan_create.restype = c_int32
@@ -189,8 +189,8 @@ def check(func: str, status: int):
         raise RadonLibError(func, status, msg)
 
 
-def geom_default(n, n_theta, n_s, m=4, q_theta=1) -> RlGeom:
+def geom_default(n, n_theta, n_s, m=4, q_theta=1, smooth=0) -> RlGeom:
     lib = load()
     g = RlGeom()
-    check("rl_geom_default", lib.rl_geom_default(n, n_theta, n_s, m, q_theta, ctypes.byref(g)))
+    check("rl_geom_default", lib.rl_geom_default(n, n_theta, n_s, m, q_theta, smooth, ctypes.byref(g)))
     return g

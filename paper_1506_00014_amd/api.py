@@ -27,13 +27,14 @@ class RadonPlan:
     m: angular partitions (beta = pi/m); n_rho, k_theta, r_dec: FFT lengths and fine
     angular oversampling (default: the smallest values meeting the paper's bounds).
     dec_filter: theta low-pass of Algorithm 1 step 4 (0 cubic B-spline, 1 box of one coarse
-    cell); q_theta: coarse lattice spacing Delta theta / q_theta (1 or 2).
+    cell); q_theta: coarse lattice spacing Delta theta / q_theta (1 or 2); smooth: default FFT
+    lengths among 2^a 3^b instead of powers of two.
     """
 
     def __init__(self, n, n_theta, n_s, m=4, n_rho=None, k_theta=None, r_dec=None, device=None, dec_filter=0,
-                 q_theta=1):
+                 q_theta=1, smooth=False):
         lib = _lib.load()
-        g = _lib.geom_default(n, n_theta, n_s, m, q_theta)
+        g = _lib.geom_default(n, n_theta, n_s, m, q_theta, 1 if smooth else 0)
         g.dec_filter = dec_filter
         if n_rho is not None:
             g.n_rho = n_rho

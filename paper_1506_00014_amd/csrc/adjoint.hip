@@ -718,7 +718,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
       rppre[nslot] = total - nfull;
     }
     // rho windows of the row copies; a window starts at a multiple of 4 and spans a multiple
-    // of 4, so rows are copied as float4 (n_rho is a power of two).  The branch-free walk
+    // of 4, so rows are copied as float4 (n_rho is a multiple of 4).  The branch-free walk
     // reads an interleaved copy [rho][row] of the rows rlo .. rhi, which covers every ray's rows
     // cg - 1 .. cg + 2 (the pass header clamps cg0, cg1 to the support; where it did, the copy
     // reaches three rows below 0 or four above the last lattice row), rows outside the

@@ -26,6 +26,19 @@ __device__ __forceinline__ void dft2(float2* v) {
   v[1] = csub(a, b);
 }
 
+// 3-point DFT: X_k = sum_j v_j w^{jk}, w = exp(-+2 pi i / 3) = -1/2 -+ i sqrt(3)/2.
+template <bool INV>
+__device__ __forceinline__ void dft3(float2* v) {
+  const float h = 0.86602540378443864676f;  // sqrt(3) / 2
+  const float2 t = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+  const float2 m = make_float2(v[0].x - 0.5f * t.x, v[0].y - 0.5f * t.y);
+  // (-+ i) sqrt(3)/2 d
+  const float2 s = INV ? make_float2(-h * d.y, h * d.x) : make_float2(h * d.y, -h * d.x);
+  v[0] = cadd(v[0], t);
+  v[1] = cadd(m, s);
+  v[2] = csub(m, s);
+}
+
 template <bool INV>
 __device__ __forceinline__ void dft4(float2* v) {
   float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
@@ -62,6 +75,7 @@ __device__ __forceinline__ void dft8(float2* v) {
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2* v) {
   if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 3) dft3<INV>(v);
   else if constexpr (R == 4) dft4<INV>(v);
   else dft8<INV>(v);
 }
@@ -69,8 +83,11 @@ __device__ __forceinline__ void dft(float2* v) {
 // Twiddles of the Stockham passes, laid out per pass (built with the plan): the pass of
 // radix R after sub-transforms of length Ns holds, for k = 0 .. Ns - 1, the R - 1 twiddles
 // exp(-2 pi i r k / (R Ns)), r = 1 .. R - 1, padded to an even count (RP entries), so that
-// a butterfly reads its twiddles as consecutive 16-byte loads.
-__host__ __device__ constexpr int stockham_radix(int left) { return left >= 8 ? 8 : (left == 4 ? 4 : 2); }
+// a butterfly reads its twiddles as consecutive 16-byte loads.  Lengths 2^a 3^b take their
+// radix-3 passes first, then radix 8, 4 and 2 as the power of two allows.
+__host__ __device__ constexpr int stockham_radix(int left) {
+  return left % 3 == 0 ? 3 : (left >= 8 ? 8 : (left == 4 ? 4 : 2));
+}
 __host__ __device__ constexpr int stockham_slots(int R) { return R == 8 ? 8 : (R == 4 ? 4 : 2); }
 
 // One Stockham pass of radix R over nfft independent FFTs of length N stored back to back
@@ -89,7 +106,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int N, int nfft, int 
     if (id < total) {
       const int f = id / nbf;
       const int j = id - f * nbf;
-      const int k = j & (Ns - 1);
+      const int k = (Ns & (Ns - 1)) == 0 ? (j & (Ns - 1)) : j % Ns;
       const float2* base = buf + f * N;
       float2 w[RP];
       if (Ns > 1) {  // uniform; the first pass multiplies by exp(0) = 1
@@ -121,7 +138,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int N, int nfft, int 
     if (id < total) {
       const int f = id / nbf;
       const int j = id - f * nbf;
-      const int k = j & (Ns - 1);
+      const int k = (Ns & (Ns - 1)) == 0 ? (j & (Ns - 1)) : j % Ns;
       float2* base = buf + f * N;
       const int o = (j - k) * R + k;
 #pragma unroll
@@ -132,7 +149,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int N, int nfft, int 
 }
 
 // Unnormalised in-place FFT (forward: exp(-2 pi i jk/N); INV: exp(+...)) of nfft
-// transforms of power-of-two length N >= 2 held in LDS; twp is the pass twiddle table of
+// transforms of length N = 2^a 3^b >= 2 held in LDS; twp is the pass twiddle table of
 // length N.  MAXV bounds the complex values per thread: nfft * N <= MAXV * blockDim.x.
 // Callers synchronise before the call.
 template <int MAXV, bool INV>
@@ -142,6 +159,7 @@ __device__ __forceinline__ void fft_lds(float2* buf, int N, int nfft, const floa
     const int R = stockham_radix(N / Ns);
     if (R == 8) stockham_pass<8, MAXV / 8, INV>(buf, N, nfft, Ns, twp);
     else if (R == 4) stockham_pass<4, MAXV / 4, INV>(buf, N, nfft, Ns, twp);
+    else if (R == 3) stockham_pass<3, (MAXV + 2) / 3, INV>(buf, N, nfft, Ns, twp);
     else stockham_pass<2, MAXV / 2, INV>(buf, N, nfft, Ns, twp);
     twp += Ns * stockham_slots(R);
     Ns *= R;
@@ -195,9 +213,12 @@ __device__ __forceinline__ void irfft_pre(float2* Z, int nc, const float2* __res
   }
 }
 
-// In-register FFT of compile-time power-of-two length R (radix-2, decimation in time with a
-// compile-time bit reversal).  Unnormalised; forward uses exp(-2 pi i jk/R), INV the
-// conjugate.  Twiddles are read from the plan's table tw[n] = exp(-2 pi i n / tw_len).
+// In-register FFT of compile-time length R = 2^a 3^b.  Unnormalised; forward uses
+// exp(-2 pi i jk/R), INV the conjugate.  Twiddles are read from the plan's table
+// tw[n] = exp(-2 pi i n / tw_len) (tw_len a multiple of R).  A factor 3 is split off first
+// (decimation in time: three interleaved sub-transforms of length R/3, then radix-3
+// butterflies with twiddles w^{s k}); a power of two runs radix-2 decimation in time with a
+// compile-time bit reversal.
 template <int R>
 constexpr int bitrev(int i) {
   int r = 0;
@@ -210,6 +231,34 @@ template <int R, bool INV>
 __device__ __forceinline__ void reg_fft(float2 (&v)[R], const float2* __restrict__ tw, int tw_len) {
   if constexpr (R == 1) {
     return;
+  } else if constexpr (R % 3 == 0) {
+    constexpr int R3 = R / 3;
+    float2 sub[3][R3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+      for (int j = 0; j < R3; ++j) sub[s][j] = v[3 * j + s];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) reg_fft<R3, INV>(sub[s], tw, tw_len);
+    const int tstep = tw_len / R;
+#pragma unroll
+    for (int k = 0; k < R3; ++k) {
+      float2 x[3];
+      x[0] = sub[0][k];
+#pragma unroll
+      for (int s = 1; s < 3; ++s) {
+        if (k == 0) {
+          x[s] = sub[s][k];
+        } else {
+          float2 w = tw[s * k * tstep];
+          if (INV) w.y = -w.y;
+          x[s] = cmul(sub[s][k], w);
+        }
+      }
+      dft3<INV>(x);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) v[k + m * R3] = x[m];
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < R; ++i) {

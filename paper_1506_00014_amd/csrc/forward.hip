@@ -631,15 +631,10 @@ rl_status prepare_forward_launches(const rl_plan* p) {
   st = ensure_dyn_lds((const void*)k_cart2lp<kFPatch>, cart2lp_lds(p->d, kFPatch), "hipFuncSetAttribute(k_cart2lp)");
   if (st != RL_OK) return st;
   switch (p->d.k_theta) {
-    case 8: return theta_prepare<8, 1>();
-    case 16: return theta_prepare<16, 1>();
-    case 32: return theta_prepare<32, 1>();
-    case 64: return theta_prepare<32, 2>();
-    case 128: return theta_prepare<32, 4>();
-    case 256: return theta_prepare<32, 8>();
-    case 512: return theta_prepare<32, 16>();
-    case 1024: return theta_prepare<32, 32>();
-    case 2048: return theta_prepare<32, 64>();
+#define RL_THETA_CASE(K, K1, K2) \
+  case K: return theta_prepare<K1, K2>();
+    RL_THETA_LENGTHS(RL_THETA_CASE)
+#undef RL_THETA_CASE
     default: return fail(RL_ERR_INTERNAL, "unsupported k_theta");
   }
 }
@@ -666,15 +661,11 @@ rl_status launch_theta_conv(const rl_plan* p, const float2* in, int in_rows, int
                             int out_rows, int out_off, int out_step, bool conj, int batch, hipStream_t s,
                             const float2* H) {
   switch (p->d.k_theta) {
-    case 8: return launch_theta_conv_t<8, 1>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
-    case 16: return launch_theta_conv_t<16, 1>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
-    case 32: return launch_theta_conv_t<32, 1>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
-    case 64: return launch_theta_conv_t<32, 2>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
-    case 128: return launch_theta_conv_t<32, 4>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
-    case 256: return launch_theta_conv_t<32, 8>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
-    case 512: return launch_theta_conv_t<32, 16>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
-    case 1024: return launch_theta_conv_t<32, 32>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
-    case 2048: return launch_theta_conv_t<32, 64>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
+#define RL_THETA_CASE(K, K1, K2) \
+  case K:                        \
+    return launch_theta_conv_t<K1, K2>(p, in, in_rows, in_off, in_step, out, out_rows, out_off, out_step, conj, batch, s, H);
+    RL_THETA_LENGTHS(RL_THETA_CASE)
+#undef RL_THETA_CASE
     default: return fail(RL_ERR_INTERNAL, "unsupported k_theta");
   }
 }

@@ -26,6 +26,30 @@ int next_pow2(long x) {
   return p;
 }
 bool is_pow2(long x) { return x > 0 && (x & (x - 1)) == 0; }
+// 2^a 3^b: the FFT lengths the Stockham and register FFTs handle
+bool is_smooth23(long x) {
+  if (x <= 0) return false;
+  while (x % 3 == 0) x /= 3;
+  return is_pow2(x);
+}
+// theta-FFT lengths with a four-step split K1 x K2 the theta pass is built for: K <= 32 with at
+// most one factor 3, or 32 K2 with K2 in {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64}
+bool theta_length_ok(long k) {
+  if (k < 8 || k > 2048 || !is_smooth23(k)) return false;
+  if (k <= 32) return k % 9 != 0;
+  if (k % 32 != 0) return false;
+  const long k2 = k / 32;
+  return k2 % 9 != 0 && k2 <= 64;
+}
+long lcm_l(long a, long b) {
+  long x = a, y = b;
+  while (y) {
+    const long t = x % y;
+    x = y;
+    y = t;
+  }
+  return a / x * b;
+}
 
 void partition_constants(int m, double* a_R, double* a_r) {
   // sec. 2, eq. (aconst), beta = pi / M
@@ -182,8 +206,8 @@ rl_status validate(const rl_geom& g) {
   if (g.n_theta < g.m || g.n_theta > 16384)
     return fail(RL_ERR_GEOMETRY, "n_theta must be in [m, 16384]");
   if (g.n_s < 2 || g.n_s > 4096) return fail(RL_ERR_GEOMETRY, "n_s must be in [2, 4096]");
-  if (!is_pow2(g.n_rho) || g.n_rho < 16 || g.n_rho > 8192)
-    return fail(RL_ERR_GEOMETRY, "n_rho must be a power of two in [16, 8192]");
+  if (!is_smooth23(g.n_rho) || g.n_rho % 4 != 0 || g.n_rho < 16 || g.n_rho > 8192)
+    return fail(RL_ERR_GEOMETRY, "n_rho must be 2^a 3^b, a multiple of 4, in [16, 8192]");
   if (g.n_rho < rho_bound(g.n, g.m))
     return fail(RL_ERR_GEOMETRY, "n_rho below the sampling bound ceil(log a_r / log(1 - 2 a_R / N))");
   int n_own = 0;
@@ -191,8 +215,10 @@ rl_status validate(const rl_geom& g) {
     auto rows = partition_rows(g.n_theta, g.m);
     for (auto& r : rows) n_own = std::max<int>(n_own, (int)r.size());
   }
-  if (!is_pow2(g.k_theta) || g.k_theta < 8 || g.k_theta > 2048)
-    return fail(RL_ERR_GEOMETRY, "k_theta must be a power of two in [8, 2048]");
+  if (!theta_length_ok(g.k_theta))
+    return fail(RL_ERR_GEOMETRY,
+                "k_theta must be in [8, 2048]: 2^a 3^b up to 32 with at most one factor 3, or 32 times one of "
+                "2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64");
   if (g.q_theta != 1 && g.q_theta != 2) return fail(RL_ERR_GEOMETRY, "q_theta must be 1 or 2");
   if (g.k_theta < 2 * g.q_theta * ((g.n_theta + g.m - 1) / g.m) ||
       g.k_theta < lattice_rows(n_own, g.q_theta) + 2 * kHalo)
@@ -335,21 +361,31 @@ WsLayout workspace_layout(const rl_plan* plan, int batch, rl_op op) {
 using namespace rl;
 
 extern "C" rl_status rl_geom_default(int32_t n, int32_t n_theta, int32_t n_s, int32_t m, int32_t q_theta,
-                                    rl_geom* out) {
+                                    int32_t smooth, rl_geom* out) {
   if (!out) return fail(RL_ERR_INVALID_ARG, "out is NULL");
-  if (n < 8 || (n & 1) || n > 8192 || m < 3 || m > kMaxPart || n_theta < m || n_s < 2 || (q_theta != 1 && q_theta != 2))
+  if (n < 8 || (n & 1) || n > 8192 || m < 3 || m > kMaxPart || n_theta < m || n_s < 2 || (q_theta != 1 && q_theta != 2) ||
+      (smooth != 0 && smooth != 1))
     return fail(RL_ERR_GEOMETRY, "no default geometry for these sizes");
   rl_geom g{};
   g.n = n;
   g.n_theta = n_theta;
   g.n_s = n_s;
   g.m = m;
-  g.n_rho = std::max(16, next_pow2(rho_bound(n, m)));
   int n_own = 0;
   auto rows = partition_rows(n_theta, m);
   for (auto& r : rows) n_own = std::max<int>(n_own, (int)r.size());
-  g.k_theta = std::max(8, next_pow2(std::max<long>(2L * q_theta * ((n_theta + m - 1) / m),
-                                                   lattice_rows(n_own, q_theta) + 2 * kHalo)));
+  const long kmin = std::max<long>(2L * q_theta * ((n_theta + m - 1) / m), lattice_rows(n_own, q_theta) + 2 * kHalo);
+  if (smooth) {
+    long nr = std::max(16L, rho_bound(n, m));
+    while (nr <= 8192 && !(is_smooth23(nr) && nr % 4 == 0)) ++nr;
+    long kt = std::max(8L, kmin);
+    while (kt <= 2048 && !theta_length_ok(kt)) ++kt;
+    g.n_rho = (int)nr;
+    g.k_theta = (int)kt;
+  } else {
+    g.n_rho = std::max(16, next_pow2(rho_bound(n, m)));
+    g.k_theta = std::max(8, next_pow2(kmin));
+  }
   g.r_dec = (int)r_bound(n, n_theta, m, q_theta);
   g.dec_filter = 0;
   g.q_theta = q_theta;
@@ -410,7 +446,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   d.nc = g.n_rho / 2;
   d.ld = d.nc + 8;
   d.lr = std::max(16, next_pow2(2L * g.n_s));
-  d.tw_len = std::max(std::max(g.n_rho, g.k_theta), d.lr);
+  // one twiddle table serves every FFT length (the rho rows, the theta pass, the ramp filter)
+  d.tw_len = (int)lcm_l(lcm_l(g.n_rho, g.k_theta), d.lr);
   plan->rows_per_part.resize(g.m);
   for (int p = 0; p < g.m; ++p) {
     plan->rows_per_part[p] = (int)rows[p].size();

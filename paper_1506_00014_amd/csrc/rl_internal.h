@@ -143,6 +143,12 @@ rl_status launch_irfft_rows(const rl_plan* p, const float2* spec, float* out, in
                             hipStream_t s);
 // The theta pass splits k_theta = K1 K2 (four-step FFT); K1 as a function of k_theta.
 constexpr int theta_k1(int k_theta) { return k_theta <= 32 ? k_theta : 32; }
+// The theta-FFT lengths the theta pass is instantiated for, as (K, K1, K2) with K = K1 K2 (the
+// plan accepts exactly these).
+#define RL_THETA_LENGTHS(X)                                                                          \
+  X(8, 8, 1) X(12, 12, 1) X(16, 16, 1) X(24, 24, 1) X(32, 32, 1) X(64, 32, 2) X(96, 32, 3) X(128, 32, 4) \
+  X(192, 32, 6) X(256, 32, 8) X(384, 32, 12) X(512, 32, 16) X(768, 32, 24) X(1024, 32, 32)          \
+  X(1536, 32, 48) X(2048, 32, 64)
 // Plan time (host): image boxes of the forward blocks, in the order of the forward grid.
 std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& cs,
                                   const std::vector<int2>& fq, const std::vector<double>& erho);

@@ -52,9 +52,9 @@ def test_defaults_match_oracle_geometry(lib, n, nt, ns):
 
 def test_argument_errors_are_status_codes(lib):
     g = _lib.RlGeom()
-    assert lib.rl_geom_default(7, 10, 10, 4, 1, ctypes.byref(g)) == 2
-    assert lib.rl_geom_default(64, 2, 64, 4, 1, ctypes.byref(g)) == 2
-    assert lib.rl_geom_default(64, 64, 64, 4, 1, None) == 1
+    assert lib.rl_geom_default(7, 10, 10, 4, 1, 0, ctypes.byref(g)) == 2
+    assert lib.rl_geom_default(64, 2, 64, 4, 1, 0, ctypes.byref(g)) == 2
+    assert lib.rl_geom_default(64, 64, 64, 4, 1, 0, None) == 1
     p = ctypes.c_void_p()
     assert lib.rl_plan_create(None, ctypes.byref(p)) == 1
     good = _lib.geom_default(64, 90, 64)
@@ -70,3 +70,37 @@ def test_argument_errors_are_status_codes(lib):
     assert lib.fbp(None, None, None, 1, 0, None, 0, None) == 1
     assert lib.rl_workspace_bytes(None, 4, 0) == 0
     lib.rl_plan_destroy(None)
+
+
+def test_fft_length_validation(lib):
+    """FFT lengths 2^a 3^b: N_rho a multiple of 4, K one of the theta pass's four-step splits.
+    A valid geometry gets past validation and fails only for want of a device here (RL_ERR_HIP);
+    an invalid one is refused with RL_ERR_GEOMETRY before any device call."""
+    p = ctypes.c_void_p()
+    base = _lib.geom_default(2048, 2048, 2048, 3)
+    cases = [("n_rho", 4608, 4), ("n_rho", 3888 * 2, 4), ("n_rho", 4374, 2), ("n_rho", 5000, 2), ("n_rho", 8192, 4), ("n_rho", 4096, 2),
+             ("k_theta", 1536, 4), ("k_theta", 1458, 2), ("k_theta", 2048, 4), ("k_theta", 3072, 2)]
+    for field, value, want in cases:
+        g = _lib.RlGeom.from_buffer_copy(base)
+        setattr(g, field, value)
+        st = lib.rl_plan_create(ctypes.byref(g), ctypes.byref(p))
+        assert st in (want, 5 if want == 4 else want), (field, value, st, lib.rl_last_error())
+        assert p.value is None
+    small = _lib.geom_default(64, 90, 64, 4)
+    for k, want in ((24, 2), (96, 4), (48, 2), (64, 4), (192, 4), (288, 2)):
+        g = _lib.RlGeom.from_buffer_copy(small)
+        g.k_theta = k
+        st = lib.rl_plan_create(ctypes.byref(g), ctypes.byref(p))
+        assert st in (want, 5 if want == 4 else want), (k, st)
+
+
+def test_smooth_defaults(lib):
+    """smooth = 1 picks the smallest 2^a 3^b lengths at or above the bounds."""
+    g = _lib.geom_default(2048, 2048, 2048, 3, 1, 1)
+    assert (g.n_rho, g.k_theta) == (4608, 1536)
+    g = _lib.geom_default(2048, 2048, 2048, 4, 1, 1)
+    assert (g.n_rho, g.k_theta) == (3888, 1024)
+    g = _lib.geom_default(128, 180, 128, 4, 1, 1)
+    assert (g.n_rho, g.k_theta) == (256, 96)
+    og = make_geometry(2048, 2048, 2048, m=3)
+    assert g.r_dec == make_geometry(128, 180, 128).r_dec and og.n_rho == 8192
