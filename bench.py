@@ -20,6 +20,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -107,17 +108,24 @@ def kernel_bytes(name, g, n_own, batch):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2048x2048_b64.txt")
 
 
-def source_digest():
-    """SHA-256 over the HIP sources and the C header: counters taken on other sources are stale."""
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1506_00014_amd", "csrc")
-    files = sorted(os.path.join(csrc, x) for x in os.listdir(csrc) if x.endswith((".hip", ".h")))
-    files.append(os.path.join(ROOT, "include", "radonlp.h"))
-    for fn in files:
-        h.update(os.path.basename(fn).encode())
-        with open(fn, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+CSRC = os.path.join(ROOT, "paper_1506_00014_amd", "csrc")
+# files every kernel's code or launch configuration depends on besides its own: the plan
+# (geometry tables, launch-parameter defaults) and the shared device headers
+COMMON_SOURCES = ("plan.hip", "rl_internal.h", "fft_device.h")
+
+
+def file_digest(name):
+    """SHA-256 of one HIP source or device header of the library."""
+    with open(os.path.join(CSRC, name), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def kernel_sources(kernel):
+    """The sources a kernel's counters depend on: the file that defines it and COMMON_SOURCES.
+    Counters taken on other versions of these files are stale; other files do not matter."""
+    pat = re.compile(r"__global__[^;{]*?\b" + re.escape(kernel) + r"\s*\(", re.S)
+    own = [f for f in sorted(os.listdir(CSRC)) if f.endswith(".hip") and pat.search(open(os.path.join(CSRC, f)).read())]
+    return own + [f for f in COMMON_SOURCES if f not in own] if own else []
 
 
 def measured_traffic(kernel, batch, n):
@@ -136,7 +144,10 @@ def measured_traffic(kernel, batch, n):
         k, v = ln.split(":", 1)
         kv[k.strip()] = v.strip()
     try:
-        if kv["source_sha256"] != source_digest() or int(kv["batch"]) != batch or int(kv["n"]) != n:
+        if int(kv["batch"]) != batch or int(kv["n"]) != n:
+            return None
+        srcs = kernel_sources(kernel)
+        if not srcs or any(kv[f"source_sha256 {f}"] != file_digest(f) for f in srcs):
             return None
         copy_bytes = float(kv["copy_bytes"])
         f_scale = copy_bytes / (1024.0 * float(kv["copy_fetch_kib"]))

@@ -128,7 +128,7 @@ typedef struct rl_plan rl_plan;
  *                    leaves behind to the LDS tile): 0 moves the footprint under branches, 1 moves
  *                    it by selects every step (uniform across a wave).  The two add the same FP32
  *                    terms in FP64 in a different order.
- * Defaults (rl_plan_create): 0, 1, 512, 1, 1, 0. */
+ * Defaults (rl_plan_create): 0, 1, 512, 1, 1, 1. */
 typedef struct {
   int32_t theta_cols;
   int32_t theta_xcd_order;

@@ -413,7 +413,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   rl_plan* plan = new rl_plan();
   plan->g = g;
   plan->device = dev;
-  plan->tune = rl_tune{0, 1, 512, 1, 1, 0};
+  plan->tune = rl_tune{0, 1, 512, 1, 1, 1};
   DevPlan& d = plan->d;
   std::memset(&d, 0, sizeof(d));
   d.n = g.n;
