@@ -346,9 +346,14 @@ rl_status rl_profile_record(int32_t i, const char** name, float* ms);
  * buffer d_sinos[i] ([n_theta][n_s]).  rl_batch_create copies the pointer lists to the device
  * and groups the slices by plan; it is synchronous and allocates.  rl_batch_fwd computes
  * d_sinos[i] = R d_imgs[i] and rl_batch_adj d_imgs[i] = R# d_sinos[i] for every slice, as one
- * batched call per plan (slices gathered into the workspace, results scattered back).  Those
- * two calls enqueue kernels on `stream` only: no allocation, host synchronisation or host
- * read, so a caller may capture them in a HIP graph and replay it with new buffer contents.
+ * batched call per plan whose first and last kernels read and write the slices' own buffers.
+ * The calls of the different plans run concurrently, each on a stream the batch owns (default
+ * priority), forked from `stream` by an event and joined back to it: when rl_batch_fwd/adj
+ * return, all their work is ordered before whatever is enqueued on `stream` next.  They
+ * enqueue event records, stream waits and kernels only: no allocation, host synchronisation or
+ * host read, so a caller may capture them on `stream` in a HIP graph (the plans' chains become
+ * parallel branches) and replay it with new buffer contents.  One batch must not be run by
+ * two calls that overlap in time (its streams and events are shared).
  * The buffers stay owned by the caller and must stay valid while the batch is used; input
  * and output buffers must not overlap.  tune_cache (optional, a file path): each plan's launch
  * parameters for the number of slices that use it are taken from that autotuner cache, or
@@ -363,7 +368,9 @@ rl_status rl_batch_create(const rl_plan* const* plans, int32_t nplans, const int
                           float* const* d_imgs, float* const* d_sinos, int32_t count, const char* tune_cache,
                           rl_batch** out);
 
-/* Workspace bytes rl_batch_fwd (op = RL_OP_FWD) or rl_batch_adj (RL_OP_ADJ) needs. */
+/* Workspace bytes rl_batch_fwd (op = RL_OP_FWD) or rl_batch_adj (RL_OP_ADJ) needs: the sum over
+ * the plans of rl_workspace_bytes(plan, slices of that plan, op), each rounded up to 256 bytes,
+ * since the plans' chains run at once in regions of their own. */
 size_t rl_batch_workspace_bytes(const rl_batch* batch, rl_op op);
 
 rl_status rl_batch_fwd(const rl_batch* batch, void* d_ws, size_t ws_bytes, hipStream_t stream);

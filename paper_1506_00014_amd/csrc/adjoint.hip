@@ -425,6 +425,126 @@ __device__ __forceinline__ void splat_walk_bf(const SegWalk2& sw, double* acc, c
   }
 }
 
+// The walk above for a wave whose lanes all run their rays in one quadrant: with the mirror
+// signs SX, SY known at compile time, the LDS element of the footprint's trailing corner is
+// kept as a running index (advanced by SX or SY kAP when the footprint moves), and every add
+// of a dropped column or row, or of the whole footprint, is one DS instruction at an immediate
+// offset from a single address (the lowest of the group; `pin` keeps the compiler from
+// folding that address back into a base with negative offsets).  Same terms, same FP64
+// additions as splat_walk_bf.
+__device__ __forceinline__ int pin(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// p[i0], p[i0 + S], p[i0 + 2 S], p[i0 + 3 S] += a, b, c, d (S of either sign)
+template <int S>
+__device__ __forceinline__ void add_line(double* acc, int i0, float a, float b, float c, float d) {
+  constexpr int lo = S < 0 ? 3 * S : 0;  // offset of the lowest element from i0
+  const int base = pin(i0 + lo);
+  atomicAdd(acc + base + (0 - lo), (double)a);
+  atomicAdd(acc + base + (S - lo), (double)b);
+  atomicAdd(acc + base + (2 * S - lo), (double)c);
+  atomicAdd(acc + base + (3 * S - lo), (double)d);
+}
+
+// the whole footprint: element i0 + j RS + i CS gets row j, column i
+template <int CS, int RS>
+__device__ __forceinline__ void add_block(double* acc, int i0, const Row4& r0, const Row4& r1, const Row4& r2,
+                                          const Row4& r3) {
+  constexpr int lo = (CS < 0 ? 3 * CS : 0) + (RS < 0 ? 3 * RS : 0);
+  const int base = pin(i0 + lo);
+  const Row4* rr[4] = {&r0, &r1, &r2, &r3};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    atomicAdd(acc + base + (j * RS - lo), (double)rr[j]->c0);
+    atomicAdd(acc + base + (j * RS + CS - lo), (double)rr[j]->c1);
+    atomicAdd(acc + base + (j * RS + 2 * CS - lo), (double)rr[j]->c2);
+    atomicAdd(acc + base + (j * RS + 3 * CS - lo), (double)rr[j]->c3);
+  }
+}
+
+template <int SX, int SY>
+__device__ __forceinline__ void splat_walk_fixed(const SegWalk2& sw, double* acc, const float* rows, int rstride,
+                                                 const double* erho, int qlo) {
+  if (sw.qend < sw.qbeg) return;
+  constexpr int CS = SX, RS = SY * kAP;
+  Row4 r0 = {0.f, 0.f, 0.f, 0.f}, r1 = r0, r2 = r0, r3 = r0;
+  int ckx, cky;
+  {
+    const double E = erho[sw.qbeg - qlo];
+    const double X = sw.X0 + E * sw.cx, Y = sw.Y0 + E * sw.cy;
+    ckx = min(max((int)floor(X), sw.lox), sw.hix);
+    cky = min(max((int)floor(Y), sw.loy), sw.hiy);
+  }
+  int ci = sw.obase + CS * (ckx - 1) + RS * (cky - 1);  // element of the trailing corner
+  const float* rp = rows + (sw.qbeg - qlo) * rstride + sw.rrow;
+  for (int q = sw.qbeg; q <= sw.qend; ++q, rp += rstride) {
+    const double E = erho[q - qlo];
+    const float V = sw.dw[0] * rp[0] + sw.dw[1] * rp[1] + sw.dw[2] * rp[2] + sw.dw[3] * rp[3];
+    const double X = sw.X0 + E * sw.cx, Y = sw.Y0 + E * sw.cy;
+    const double fx = floor(X), fy = floor(Y);
+    const int kx = min(max((int)fx, sw.lox), sw.hix);
+    const int ky = min(max((int)fy, sw.loy), sw.hiy);
+    if (((unsigned)(kx - ckx) | (unsigned)(ky - cky)) > 1u) {  // (see splat_walk_bf)
+      add_block<CS, RS>(acc, ci, r0, r1, r2, r3);
+      r0 = Row4{0.f, 0.f, 0.f, 0.f};
+      r1 = r0;
+      r2 = r0;
+      r3 = r0;
+      ckx = kx;
+      cky = ky;
+      ci = sw.obase + CS * (kx - 1) + RS * (ky - 1);
+    }
+    const bool mx = kx != ckx, my = ky != cky;
+    if (mx) add_line<RS>(acc, ci, r0.c0, r1.c0, r2.c0, r3.c0);  // drop column 0
+    const unsigned long long bx = __builtin_amdgcn_ballot_w64(mx), by = __builtin_amdgcn_ballot_w64(my);
+    const float zero = 0.f;
+#define RL_SHIFT_X(r)                   \
+  r.c0 = lane_select(r.c0, r.c1, bx);   \
+  r.c1 = lane_select(r.c1, r.c2, bx);   \
+  r.c2 = lane_select(r.c2, r.c3, bx);   \
+  r.c3 = lane_select(r.c3, zero, bx);
+    RL_SHIFT_X(r0)
+    RL_SHIFT_X(r1)
+    RL_SHIFT_X(r2)
+    RL_SHIFT_X(r3)
+#undef RL_SHIFT_X
+    ci += mx ? CS : 0;
+    if (my) add_line<CS>(acc, ci, r0.c0, r0.c1, r0.c2, r0.c3);  // drop row 0
+#define RL_SHIFT_Y(c)                   \
+  r0.c = lane_select(r0.c, r1.c, by);   \
+  r1.c = lane_select(r1.c, r2.c, by);   \
+  r2.c = lane_select(r2.c, r3.c, by);   \
+  r3.c = lane_select(r3.c, zero, by);
+    RL_SHIFT_Y(c0)
+    RL_SHIFT_Y(c1)
+    RL_SHIFT_Y(c2)
+    RL_SHIFT_Y(c3)
+#undef RL_SHIFT_Y
+    ci += my ? RS : 0;
+    ckx = kx;
+    cky = ky;
+    float wx[4], wy[4];
+    bspline_w6((float)(X - fx), wx);
+    bspline_w6((float)(Y - fy), wy);
+#define RL_ACC(r, j)                         \
+  {                                          \
+    const float vy = V * wy[j];              \
+    r.c0 = fmaf(vy, wx[0], r.c0);            \
+    r.c1 = fmaf(vy, wx[1], r.c1);            \
+    r.c2 = fmaf(vy, wx[2], r.c2);            \
+    r.c3 = fmaf(vy, wx[3], r.c3);            \
+  }
+    RL_ACC(r0, 0)
+    RL_ACC(r1, 1)
+    RL_ACC(r2, 2)
+    RL_ACC(r3, 3)
+#undef RL_ACC
+  }
+  add_block<CS, RS>(acc, ci, r0, r1, r2, r3);
+}
+
 // ---- splat passes, built once per plan
 // A pass is one partition m, one periodic shift (sx, sy) of one tile and up to kARows fine
 // rays ta .. ta + nrows - 1, laid out in ray slots (slot of ray k: (k % kRayGap) * ng +
@@ -817,7 +937,23 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
           sw.dw[2] = dw.z * (1.0f / 36.0f);
           sw.dw[3] = dw.w * (1.0f / 36.0f);
           sw.rrow = rcg[k] - 1 - rlo;
-          splat_walk_bf(sw, acc, us, nur, es, wq4);
+          // lanes that all run their rays in one quadrant take the walk with compile-time
+          // mirror signs (wave-uniform branch); a wave with mixed quadrants the general one
+          const unsigned long long act = __builtin_amdgcn_ballot_w64(true);
+          const unsigned long long bxp = __builtin_amdgcn_ballot_w64(xp), byp = __builtin_amdgcn_ballot_w64(yp);
+          if ((bxp == 0 || bxp == act) && (byp == 0 || byp == act)) {
+            const bool wx = __builtin_amdgcn_readfirstlane((int)xp) != 0;
+            const bool wy = __builtin_amdgcn_readfirstlane((int)yp) != 0;
+            if (wx) {
+              if (wy) splat_walk_fixed<1, 1>(sw, acc, us, nur, es, wq4);
+              else splat_walk_fixed<1, -1>(sw, acc, us, nur, es, wq4);
+            } else {
+              if (wy) splat_walk_fixed<-1, 1>(sw, acc, us, nur, es, wq4);
+              else splat_walk_fixed<-1, -1>(sw, acc, us, nur, es, wq4);
+            }
+          } else {
+            splat_walk_bf(sw, acc, us, nur, es, wq4);
+          }
           continue;
         }
         SegWalk sw;

@@ -1,7 +1,11 @@
 // Ragged batches: slices of several geometries.  The slices of one plan run as one batched
 // call of its operator chain whose first and last kernels address each slice's own buffer
 // through a device table of pointers (built once by rl_batch_create), so no slice is copied.
-// Everything after rl_batch_create is kernel launches on the caller's stream (graph-capturable).
+// The chains of the plans run concurrently: each on a stream of its own (created with the
+// batch, default priority), forked from the caller's stream by an event and joined back to it
+// by one event per chain, each chain in its own region of the workspace.  Everything after
+// rl_batch_create is event records, stream waits and kernel launches, so a call captured on
+// the caller's stream becomes one graph with the chains as parallel branches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,11 +24,16 @@ struct rl_batch {
   int count;
   std::vector<Group> groups;
   float** d_ptrs;  // [2][count]: image pointers, then sinogram pointers, in group order
+  std::vector<hipStream_t> streams;  // one per group
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;     // one per group
 };
 
 namespace {
 
-size_t group_ws(const rl_batch::Group& g, rl_op op) { return rl_workspace_bytes(g.plan, g.count, op); }
+size_t group_ws(const rl_batch::Group& g, rl_op op) {
+  return (rl_workspace_bytes(g.plan, g.count, op) + 255) & ~(size_t)255;
+}
 
 // Run `op` on the group's slices as one batch, reading and writing the slices in place.
 rl_status run_group(const rl_batch* b, const rl_batch::Group& g, bool fwd, void* ws, hipStream_t s) {
@@ -46,11 +55,22 @@ rl_status batch_run(const rl_batch* b, bool fwd, void* d_ws, size_t ws_bytes, hi
   const size_t need = rl_batch_workspace_bytes(b, fwd ? RL_OP_FWD : RL_OP_ADJ);
   if (!d_ws || ws_bytes < need) return fail(RL_ERR_WORKSPACE, "workspace smaller than rl_batch_workspace_bytes");
   if (((uintptr_t)d_ws & 255) != 0) return fail(RL_ERR_WORKSPACE, "workspace is not 256-byte aligned");
-  for (const auto& g : b->groups) {
-    rl_status st = run_group(b, g, fwd, d_ws, s);
-    if (st != RL_OK) return st;
+  const rl_op op = fwd ? RL_OP_FWD : RL_OP_ADJ;
+  rl_status st = check_hip(hipEventRecord(b->fork, s), "hipEventRecord(batch fork)");
+  size_t off = 0;
+  for (size_t i = 0; i < b->groups.size() && st == RL_OK; ++i) {
+    const auto& g = b->groups[i];
+    hipStream_t gs = b->streams[i];
+    st = check_hip(hipStreamWaitEvent(gs, b->fork, 0), "hipStreamWaitEvent(batch fork)");
+    if (st != RL_OK) break;
+    st = run_group(b, g, fwd, (char*)d_ws + off, gs);
+    // a chain that was forked is joined back even when one of its launches failed
+    rl_status jt = check_hip(hipEventRecord(b->joins[i], gs), "hipEventRecord(batch join)");
+    if (jt == RL_OK) jt = check_hip(hipStreamWaitEvent(s, b->joins[i], 0), "hipStreamWaitEvent(batch join)");
+    if (st == RL_OK) st = jt;
+    off += group_ws(g, op);
   }
-  return RL_OK;
+  return st;
 }
 
 }  // namespace
@@ -92,14 +112,29 @@ extern "C" rl_status rl_batch_create(const rl_plan* const* plans, int32_t nplans
     if (g.count == 0) continue;
     b->groups.push_back(g);
   }
+  {
+    // the chains' streams (default priority, not synchronising with the null stream) and events
+    rl_status st = check_hip(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "hipEventCreate(batch)");
+    for (size_t i = 0; i < b->groups.size() && st == RL_OK; ++i) {
+      hipStream_t gs = nullptr;
+      hipEvent_t ev = nullptr;
+      st = check_hip(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking), "hipStreamCreate(batch)");
+      if (st == RL_OK) b->streams.push_back(gs);
+      if (st == RL_OK) st = check_hip(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate(batch)");
+      if (st == RL_OK) b->joins.push_back(ev);
+    }
+    if (st != RL_OK) {
+      rl_batch_destroy(b);
+      return st;
+    }
+  }
   if (count > 0) {
     rl_status st = check_hip(hipMalloc((void**)&b->d_ptrs, sizeof(float*) * ptrs.size()), "hipMalloc(batch)");
     if (st == RL_OK)
       st = check_hip(hipMemcpy(b->d_ptrs, ptrs.data(), sizeof(float*) * ptrs.size(), hipMemcpyHostToDevice),
                      "upload batch pointers");
     if (st != RL_OK) {
-      if (b->d_ptrs) (void)hipFree(b->d_ptrs);
-      delete b;
+      rl_batch_destroy(b);
       return st;
     }
   }
@@ -126,8 +161,8 @@ extern "C" rl_status rl_batch_create(const rl_plan* const* plans, int32_t nplans
 
 extern "C" size_t rl_batch_workspace_bytes(const rl_batch* batch, rl_op op) {
   if (!batch) return 0;
-  size_t need = 0;
-  for (const auto& g : batch->groups) need = std::max(need, group_ws(g, op));
+  size_t need = 0;  // the chains run concurrently: one region each
+  for (const auto& g : batch->groups) need += group_ws(g, op);
   return need;
 }
 
@@ -142,5 +177,8 @@ extern "C" rl_status rl_batch_adj(const rl_batch* batch, void* d_ws, size_t ws_b
 extern "C" void rl_batch_destroy(rl_batch* batch) {
   if (!batch) return;
   if (batch->d_ptrs) (void)hipFree(batch->d_ptrs);
+  for (hipStream_t gs : batch->streams) (void)hipStreamDestroy(gs);
+  for (hipEvent_t ev : batch->joins) (void)hipEventDestroy(ev);
+  if (batch->fork) (void)hipEventDestroy(batch->fork);
   delete batch;
 }

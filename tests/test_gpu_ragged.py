@@ -59,34 +59,45 @@ def test_ragged_matches_plain_calls(setup):
         assert err <= 1e-6  # FP64 LDS accumulation: summation order may differ
 
 
-def test_ragged_graph_replay(setup):
-    """Capture one forward of the batch, replay it after changing the inputs in place, with
-    eager work and synchronisations between replays; every replay equals eager calls."""
+@pytest.mark.parametrize("op", ["forward", "adjoint"])
+def test_ragged_graph_replay(setup, op):
+    """Capture one call of the batch (the plans' chains as parallel branches forked from and
+    joined to the capturing stream), replay it after changing the inputs in place, with eager
+    work and synchronisations between replays; every replay equals eager per-slice calls."""
     from paper_1506_00014_amd import RaggedBatch
 
     dev, plans = setup
     items = make_items(dev, plans, 600)
     batch = RaggedBatch(items)
-    batch.forward()  # warm-up outside the capture
+    run = getattr(batch, op)
+    run()  # warm-up outside the capture
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         with torch.cuda.graph(graph, stream=s):
-            batch.forward()
+            run()
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     for rep in range(3):
         for i, (plan, img, sino) in enumerate(items):
-            n = img.shape[0]
-            img.copy_(torch.tensor(inputs.ellipse_phantom(n, 4, 700 + 10 * rep + i)[0], dtype=torch.float32))
-            sino.zero_()
+            n, nt, ns = img.shape[0], sino.shape[0], sino.shape[1]
+            if op == "forward":
+                img.copy_(torch.tensor(inputs.ellipse_phantom(n, 4, 700 + 10 * rep + i)[0], dtype=torch.float32))
+                sino.zero_()
+            else:
+                sino.copy_(torch.tensor(inputs.normal_array((nt, ns), 900 + 10 * rep + i), dtype=torch.float32))
+                img.zero_()
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
         for plan, img, sino in items:
-            assert torch.equal(sino, plan.forward(img))
+            if op == "forward":
+                assert torch.equal(sino, plan.forward(img))
+            else:
+                ref = plan.adjoint(sino)
+                assert (img - ref).abs().max().item() <= 1e-6 * ref.abs().max().item()
         _ = torch.ones(1000, device=dev).sum().item()  # eager work between replays
 
 
