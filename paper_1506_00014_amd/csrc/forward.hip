@@ -141,6 +141,11 @@ constexpr int kFQ = 64;         // rho indices per block: one per lane of a wave
 constexpr int kFRows = 8;       // coarse rows per block
 constexpr int kFPatch = 8448;   // floats of the LDS image patch (large tiles)
 constexpr int kFPatchSmall = 5504;  // patch of the small tiles: four blocks per CU fit in LDS
+// Row pitches of the two patches (odd, so that rows spread over the LDS banks).  A fixed pitch
+// puts the 16 taps of a sample at compile-time offsets from one address.  A box is staged when
+// its width fits the pitch and its height PATCH / PITCH rows.
+constexpr int kFPitch = 93;
+constexpr int kFPitchSmall = 77;
 constexpr int kFThreads = 512;  // threads per block
 static_assert(kFQ == 64, "the sample loop maps rho indices to the lanes of a wave");
 
@@ -169,7 +174,7 @@ __device__ __forceinline__ float bicubic_at(double X, double Y, int n, Tap tap) 
 //    samples of one fine ray at a time, a lane per rho index, into an LDS buffer; samples
 //    outside D are zero.  3) Each coarse sample is the decimation filter over the fine rows
 //    around it, times e^rho.
-template <int PATCH>
+template <int PATCH, int PITCH>
 __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __restrict__ tiles,
                                                         const float* __restrict__ c, float* __restrict__ u,
                                                         int xcd_order) {
@@ -227,8 +232,7 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __r
   }
   if (threadIdx.x < kFQ) se[threadIdx.x] = q0 + (int)threadIdx.x <= qlast ? P.erho[q0 + threadIdx.x] : 0.0;
   const int Xlo = box.x, Ylo = box.y, W = box.z, H = box.w;
-  const int Wp = W | 1;  // odd pitch spreads rows over the LDS banks
-  const bool staged = Wp * H <= PATCH;
+  const bool staged = (W | 1) <= PITCH && H <= PATCH / PITCH;
   {
     if (staged) {
       // groups of four consecutive pixels in flat order; (ly, lg) advance by the block stride
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __r
               }
               v[u] = make_float4(t[0], t[1], t[2], t[3]);
             }
-            dsti[u] = ly * Wp + 4 * lg;
+            dsti[u] = ly * PITCH + 4 * lg;
           }
           ly += dly;
           lg += dlg;
@@ -303,11 +307,11 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __r
       bspline_w6((float)(Y - fy), wy);
       const unsigned bx = min((unsigned)((int)fx - 1 - Xlo), (unsigned)(W - 4));
       const unsigned by = min((unsigned)((int)fy - 1 - Ylo), (unsigned)(H - 4));
-      const float* p0 = patch + __umul24(by, (unsigned)Wp) + bx;
+      const float* p0 = patch + __umul24(by, (unsigned)PITCH) + bx;
       float v = 0.f;
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
-        const float* pr = p0 + bb * Wp;
+        const float* pr = p0 + bb * PITCH;
         v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
       }
       const bool in = tl < nft && q <= qlast && q >= qr.x && q <= qr.y;
@@ -422,13 +426,13 @@ rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, 
   const int n_small = p->tune.fwd_patch_split ? d.ftiles_small : 0;
   const int n_large = d.ftiles_small + d.ftiles_large - n_small;
   if (n_small > 0) {
-    hipLaunchKernelGGL(k_cart2lp<kFPatchSmall>, dim3(n_small, batch), dim3(kFThreads),
+    hipLaunchKernelGGL((k_cart2lp<kFPatchSmall, kFPitchSmall>), dim3(n_small, batch), dim3(kFThreads),
                        cart2lp_lds(d, kFPatchSmall), s, d, d.ftiles, c, u, p->tune.fwd_xcd_order);
     st = check_launch("k_cart2lp");
   }
   if (st == RL_OK && n_large > 0) {
-    hipLaunchKernelGGL(k_cart2lp<kFPatch>, dim3(n_large, batch), dim3(kFThreads), cart2lp_lds(d, kFPatch), s,
-                       d, d.ftiles + n_small, c, u, p->tune.fwd_xcd_order);
+    hipLaunchKernelGGL((k_cart2lp<kFPatch, kFPitch>), dim3(n_large, batch), dim3(kFThreads),
+                       cart2lp_lds(d, kFPatch), s, d, d.ftiles + n_small, c, u, p->tune.fwd_xcd_order);
     st = check_launch("k_cart2lp");
   }
   prof_close(slot, s);
@@ -440,7 +444,8 @@ std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small) {
   std::vector<int> small, large;
   for (int t = 0; t < (int)boxes.size(); ++t) {
     const int4 bx = boxes[t];
-    ((bx.z == 0 || (bx.z | 1) * bx.w <= kFPatchSmall) ? small : large).push_back(t);
+    const bool fits_small = (bx.z | 1) <= kFPitchSmall && bx.w <= kFPatchSmall / kFPitchSmall;
+    ((bx.z == 0 || fits_small) ? small : large).push_back(t);
   }
   *n_small = (int)small.size();
   small.insert(small.end(), large.begin(), large.end());
@@ -625,10 +630,11 @@ static rl_status theta_prepare() {
 }
 
 rl_status prepare_forward_launches(const rl_plan* p) {
-  rl_status st = ensure_dyn_lds((const void*)k_cart2lp<kFPatchSmall>, cart2lp_lds(p->d, kFPatchSmall),
+  rl_status st = ensure_dyn_lds((const void*)k_cart2lp<kFPatchSmall, kFPitchSmall>, cart2lp_lds(p->d, kFPatchSmall),
                                 "hipFuncSetAttribute(k_cart2lp)");
   if (st != RL_OK) return st;
-  st = ensure_dyn_lds((const void*)k_cart2lp<kFPatch>, cart2lp_lds(p->d, kFPatch), "hipFuncSetAttribute(k_cart2lp)");
+  st = ensure_dyn_lds((const void*)k_cart2lp<kFPatch, kFPitch>, cart2lp_lds(p->d, kFPatch),
+                      "hipFuncSetAttribute(k_cart2lp)");
   if (st != RL_OK) return st;
   switch (p->d.k_theta) {
 #define RL_THETA_CASE(K, K1, K2) \
