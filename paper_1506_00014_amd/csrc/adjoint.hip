@@ -46,15 +46,20 @@ __global__ __launch_bounds__(kThreads) void k_splat_rfft(DevPlan P, Slices<const
   const int2* tr = P.tau + ((size_t)m * P.n_own + o) * ns;  // rho position of each sample
   for (int q = threadIdx.x; q < nr; q += blockDim.x) acc[q] = 0.0;
   __syncthreads();
-  for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-    const float g = src[k] * inv_aR;
-    const int2 t = tr[k];
-    const int kq = t.x;
-    float w[4];
-    bspline_w6(__int_as_float(t.y), w);
+  struct Sample {
+    float g;
+    int2 t;
+  };
+  row_copy(
+      ns, [&](int k) { return Sample{src[k], tr[k]}; },
+      [&](int, Sample sm) {
+        const float g = sm.g * inv_aR;
+        const int kq = sm.t.x;
+        float w[4];
+        bspline_w6(__int_as_float(sm.t.y), w);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) atomicAdd(&acc[wrap1(kq - 1 + a, nr)], (double)(w[a] * g));
-  }
+        for (int a = 0; a < 4; ++a) atomicAdd(&acc[wrap1(kq - 1 + a, nr)], (double)(w[a] * g));
+      });
   __syncthreads();
   // FP64 -> FP32 in place: every thread reads its entries before any is overwritten
   constexpr int kPer = 2 * kRowVals;  // n_rho <= kPer * blockDim.x (checked at plan time)
@@ -104,10 +109,9 @@ __global__ __launch_bounds__(kThreads) void k_irfft_scale(DevPlan P, const float
   fft_lds<kRowVals, true>(sh, nc, 1, P.twp_rows);
   const float* x = reinterpret_cast<const float*>(sh);
   float* dst = u + row * P.n_rho;
-  for (int q = threadIdx.x; q < P.n_rho; q += blockDim.x) {
-    const float er = (float)(P.erho[q] * (P.a_R * P.dx));
-    dst[q] = x[q] * er;
-  }
+  const double e_scale = P.a_R * P.dx;
+  row_copy(
+      P.n_rho, [&](int q) { return P.erho[q]; }, [&](int q, double e) { dst[q] = x[q] * (float)(e * e_scale); });
 }
 
 rl_status launch_irfft_scale(const rl_plan* p, const float2* spec, float* u, int batch, hipStream_t s) {
@@ -1015,43 +1019,56 @@ __global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __res
   const size_t row = blockIdx.x;
   float* xs = reinterpret_cast<float*>(sh);
   const float* src = in + row * ns;
-  for (int i = threadIdx.x; i < P.lr; i += blockDim.x) xs[i] = i < ns ? src[i] : 0.f;
+  row_copy(
+      P.lr, [&](int i) { return src[min(i, ns - 1)]; }, [&](int i, float v) { xs[i] = i < ns ? v : 0.f; });
   __syncthreads();
   fft_lds<kRowVals, false>(sh, ncr, 1, P.twp_ramp);
   const int step = P.tw_len / P.lr;
   const float* mult = P.ramp + (size_t)filter * (ncr + 1);
-  for (int k = threadIdx.x; k <= ncr / 2; k += blockDim.x) {
-    const int km = ncr - k;
-    const float2 a = sh[k];
-    const float2 bz = sh[k == 0 ? 0 : km];
-    // forward packing -> X[k], X[km]
-    auto post = [&](float2 za, float2 zb, int kk) {
-      const float2 e = cscale(cadd(za, cconj(zb)), 0.5f);
-      const float2 o = cscale(csub(za, cconj(zb)), 0.5f);
-      const float2 w = P.tw[kk * step];
-      const float2 t = cmul(w, o);
-      return make_float2(e.x + t.y, e.y - t.x);
-    };
-    float2 Xk = post(a, bz, k);
-    float2 Xm = post(bz, a, km);
-    Xk = cscale(Xk, mult[k]);
-    Xm = cscale(Xm, mult[km]);
-    // inverse packing from (Y[k], Y[km])
-    auto pre = [&](float2 ya, float2 yb, int kk) {
-      const float2 bb = cconj(yb);
-      const float2 e = cadd(ya, bb), dd = csub(ya, bb);
-      float2 w = P.tw[kk * step];
-      w.y = -w.y;
-      const float2 oo = cmul(dd, w);
-      return make_float2(e.x - oo.y, e.y + oo.x);
-    };
-    const float2 Zk = pre(Xk, Xm, k);
-    if (k == 0) {
-      sh[0] = Zk;
-    } else {
-      const float2 Zm = pre(Xm, Xk, km);
-      sh[k] = Zk;
-      sh[km] = Zm;
+  const int half = ncr / 2;
+  // forward packing -> X[k], X[km] (w: the twiddle of kk)
+  auto post = [&](float2 za, float2 zb, float2 w) {
+    const float2 e = cscale(cadd(za, cconj(zb)), 0.5f);
+    const float2 o = cscale(csub(za, cconj(zb)), 0.5f);
+    const float2 t = cmul(w, o);
+    return make_float2(e.x + t.y, e.y - t.x);
+  };
+  // inverse packing from (Y[k], Y[km])
+  auto pre = [&](float2 ya, float2 yb, float2 w) {
+    const float2 bb = cconj(yb);
+    const float2 e = cadd(ya, bb), dd = csub(ya, bb);
+    const float2 oo = cmul(dd, cconj(w));
+    return make_float2(e.x - oo.y, e.y + oo.x);
+  };
+  for (int base = 0; base <= half; base += kChunk * (int)blockDim.x) {
+    float2 wk[kChunk], wm[kChunk];
+    float mk[kChunk], mm[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {  // the chunk's twiddles and multipliers (global) first
+      const int k = min(base + (int)threadIdx.x + c * (int)blockDim.x, half);
+      const int km = ncr - k;
+      wk[c] = P.tw[k * step];
+      wm[c] = P.tw[km * step];
+      mk[c] = mult[k];
+      mm[c] = mult[km];
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int k = base + (int)threadIdx.x + c * (int)blockDim.x;
+      if (k > half) continue;
+      const int km = ncr - k;
+      const float2 a = sh[k];
+      const float2 bz = sh[k == 0 ? 0 : km];
+      const float2 Xk = cscale(post(a, bz, wk[c]), mk[c]);
+      const float2 Xm = cscale(post(bz, a, wm[c]), mm[c]);
+      const float2 Zk = pre(Xk, Xm, wk[c]);
+      if (k == 0) {
+        sh[0] = Zk;
+      } else {
+        const float2 Zm = pre(Xm, Xk, wm[c]);
+        sh[k] = Zk;
+        sh[km] = Zm;
+      }
     }
   }
   __syncthreads();

@@ -65,10 +65,10 @@ __global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const floa
                                    // (dead once cs is built; x then takes its place)
   float* cs = x + max(nr, nw);     // [nw] its spline coefficients, same indexing
   const float* src = sino + ((size_t)b * P.n_theta + j) * ns;
-  for (int i = threadIdx.x; i < nw; i += blockDim.x) {
-    const int k = i - kBpPad;
-    gs[i] = (k >= 0 && k < ns) ? src[k] : 0.f;
-  }
+  row_copy(
+      nw,
+      [&](int i) { return src[min(max(i - kBpPad, 0), ns - 1)]; },
+      [&](int i, float v) { gs[i] = (i >= kBpPad && i < ns + kBpPad) ? v : 0.f; });
   __syncthreads();
   // c_i = sum_{|d| <= kPrefR} pref_|d| g_{i+d}: a thread computes kFirRun consecutive outputs
   // from one window of inputs in registers
@@ -94,8 +94,8 @@ __global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const floa
   const double cth = P.own_cos[m * P.n_own + o];
   const double c0 = (1.0 - P.a_R) * cth, e_scale = P.a_R * P.dx, inv_aR = 1.0 / P.a_R;
   const double inv_ds = 1.0 / P.ds;
-  for (int q = threadIdx.x; q < nr; q += blockDim.x) {
-    double s = (P.erho[q] * e_scale - c0) * inv_aR;  // line offset of lattice node (theta', rho_q)
+  row_copy(nr, [&](int q) { return P.erho[q]; }, [&](int q, double erq) {
+    double s = (erq * e_scale - c0) * inv_aR;  // line offset of lattice node (theta', rho_q)
     if (wrap) s = -s;
     const double t = (s + 1.0) * inv_ds;  // index position along s
     float v = 0.f;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const floa
       v *= (1.0f / 6.0f);
     }
     x[q] = v;
-  }
+  });
   __syncthreads();
   fft_lds<kRowVals, false>(sh, nc, 1, P.twp_rows);
   rfft_post(sh, nc, P.tw, P.tw_len, [&](int k, float2 xv) { dst[k] = xv; });

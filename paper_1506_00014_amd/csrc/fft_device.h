@@ -166,6 +166,30 @@ __device__ __forceinline__ void fft_lds(float2* buf, int N, int nfft, const floa
   }
 }
 
+// Values a thread handles per chunk in the row loops below.  A loop over a row with a global
+// load per iteration would wait a full memory round trip per iteration (nothing lets the
+// compiler overlap iterations of a loop whose trip count is unknown); these loops issue all
+// loads of a chunk first, then consume them.
+constexpr int kChunk = 8;
+
+// For i in [0, n), strided over the block: put(i, get(i)), the gets of a chunk issued together
+// (unconditionally: an index past the end reads entry n - 1, unused, so that no branch splits
+// the loads).  n >= 1.
+template <class Get, class Put>
+__device__ __forceinline__ void row_copy(int n, Get get, Put put) {
+  using T = decltype(get(0));
+  for (int base = 0; base < n; base += kChunk * (int)blockDim.x) {
+    T v[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) v[c] = get(min(base + (int)threadIdx.x + c * (int)blockDim.x, n - 1));
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int i = base + (int)threadIdx.x + c * (int)blockDim.x;
+      if (i < n) put(i, v[c]);
+    }
+  }
+}
+
 // Real FFT post-processing: Z = FFT_nc(x[2n] + i x[2n+1]) in LDS -> X[k], k = 0..nc, of the
 // length-2nc real signal.  Calls fn(k, X[k]) for every k in [0, nc].  Threads stride over
 // k in [0, nc/2]; each handles k and nc - k.
@@ -173,23 +197,34 @@ template <class Fn>
 __device__ __forceinline__ void rfft_post(const float2* Z, int nc, const float2* __restrict__ tw,
                                           int tw_len, Fn fn) {
   const int step = tw_len / (2 * nc);
-  for (int k = threadIdx.x; k <= nc / 2; k += blockDim.x) {
-    const int km = nc - k;
-    float2 a = Z[k == 0 ? 0 : k];
-    float2 b = Z[k == 0 ? 0 : km];
-    // X[k] = (a + conj b)/2 - i/2 w^k (a - conj b),  w = exp(-2 pi i / (2 nc))
-    float2 e = cscale(cadd(a, cconj(b)), 0.5f);
-    float2 o = cscale(csub(a, cconj(b)), 0.5f);
-    float2 w = tw[k * step];
-    float2 t = cmul(w, o);
-    fn(k, make_float2(e.x + t.y, e.y - t.x));
-    if (km != k) {
-      // X[nc - k] from the same pair with roles swapped
-      float2 e2 = cscale(cadd(b, cconj(a)), 0.5f);
-      float2 o2 = cscale(csub(b, cconj(a)), 0.5f);
-      float2 w2 = (km == nc) ? make_float2(-1.f, 0.f) : tw[km * step];
-      float2 t2 = cmul(w2, o2);
-      fn(km, make_float2(e2.x + t2.y, e2.y - t2.x));
+  const int half = nc / 2;
+  for (int base = 0; base <= half; base += kChunk * (int)blockDim.x) {
+    float2 w1[kChunk], w2[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {  // twiddles of the chunk (global) first, unconditionally
+      const int k = min(base + (int)threadIdx.x + c * (int)blockDim.x, half);
+      w1[c] = tw[k * step];
+      w2[c] = tw[(nc - k) * step];  // k = 0: exp(-i pi) = -1
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int k = base + (int)threadIdx.x + c * (int)blockDim.x;
+      if (k > half) continue;
+      const int km = nc - k;
+      const float2 a = Z[k == 0 ? 0 : k];
+      const float2 b = Z[k == 0 ? 0 : km];
+      // X[k] = (a + conj b)/2 - i/2 w^k (a - conj b),  w = exp(-2 pi i / (2 nc))
+      const float2 e = cscale(cadd(a, cconj(b)), 0.5f);
+      const float2 o = cscale(csub(a, cconj(b)), 0.5f);
+      const float2 t = cmul(w1[c], o);
+      fn(k, make_float2(e.x + t.y, e.y - t.x));
+      if (km != k) {
+        // X[nc - k] from the same pair with roles swapped
+        const float2 e2 = cscale(cadd(b, cconj(a)), 0.5f);
+        const float2 o2 = cscale(csub(b, cconj(a)), 0.5f);
+        const float2 t2 = cmul(km == nc ? make_float2(-1.f, 0.f) : w2[c], o2);
+        fn(km, make_float2(e2.x + t2.y, e2.y - t2.x));
+      }
     }
   }
 }
@@ -201,15 +236,27 @@ template <class Get>
 __device__ __forceinline__ void irfft_pre(float2* Z, int nc, const float2* __restrict__ tw,
                                           int tw_len, Get get) {
   const int step = tw_len / (2 * nc);
-  for (int k = threadIdx.x; k < nc; k += blockDim.x) {
-    float2 a = get(k);
-    float2 b = cconj(get(nc - k));
-    float2 e = cadd(a, b);
-    float2 d = csub(a, b);
-    float2 w = tw[k * step];
-    w.y = -w.y;                 // exp(+2 pi i k / (2 nc))
-    float2 o = cmul(d, w);
-    Z[k] = make_float2(e.x - o.y, e.y + o.x);   // e + i o
+  for (int base = 0; base < nc; base += kChunk * (int)blockDim.x) {
+    float2 xa[kChunk], xb[kChunk], w[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {  // every load of the chunk first, unconditionally
+      const int k = min(base + (int)threadIdx.x + c * (int)blockDim.x, nc - 1);
+      xa[c] = get(k);
+      xb[c] = get(nc - k);
+      w[c] = tw[k * step];
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int k = base + (int)threadIdx.x + c * (int)blockDim.x;
+      if (k >= nc) continue;
+      const float2 a = xa[c];
+      const float2 b = cconj(xb[c]);
+      const float2 e = cadd(a, b);
+      const float2 d = csub(a, b);
+      const float2 wc = cconj(w[c]);  // exp(+2 pi i k / (2 nc))
+      const float2 o = cmul(d, wc);
+      Z[k] = make_float2(e.x - o.y, e.y + o.x);  // e + i o
+    }
   }
 }
 

@@ -460,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void k_rfft_rows(DevPlan P, const float* 
   const int nc = P.nc;
   const size_t row = blockIdx.x;
   const float2* src = reinterpret_cast<const float2*>(in + row * P.n_rho);
-  for (int i = threadIdx.x; i < nc; i += blockDim.x) sh[i] = src[i];
+  row_copy(nc, [&](int i) { return src[i]; }, [&](int i, float2 v) { sh[i] = v; });
   __syncthreads();
   fft_lds<kRowVals, false>(sh, nc, 1, P.twp_rows);
   float2* dst = out + row * P.ld;
@@ -539,7 +539,8 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
         const int lr = K2 * n1 + n2 - in_off;
         const int ir = in_step == 1 ? lr : lr >> 1;
         const bool hit = lr >= 0 && (in_step == 1 || (lr & 1) == 0) && ir < in_rows;
-        x[n1] = hit ? src[(size_t)ir * P.ld + col] : make_float2(0.f, 0.f);
+        // (a 24-bit product: rows and their stride are far below 2^24)
+        x[n1] = hit ? src[__umul24((unsigned)ir, (unsigned)P.ld) + col] : make_float2(0.f, 0.f);
       }
       reg_fft<K1, false>(x, P.tw, P.tw_len);
     }
@@ -603,7 +604,8 @@ __global__ __launch_bounds__(kThreads) void k_theta_conv(DevPlan P, const float2
       for (int n1 = 0; n1 < K1; ++n1) {
         const int lr = K2 * n1 + n2 - out_off;
         const int orow = out_step == 1 ? lr : lr >> 1;
-        if (lr >= 0 && (out_step == 1 || (lr & 1) == 0) && orow < out_rows) dst[(size_t)orow * P.ld + col] = x[n1];
+        if (lr >= 0 && (out_step == 1 || (lr & 1) == 0) && orow < out_rows)
+          dst[__umul24((unsigned)orow, (unsigned)P.ld) + col] = x[n1];
       }
     }
   }
@@ -696,16 +698,17 @@ __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2
   const float inv_aR = (float)(scale / (6.0 * P.a_R));  // 1/a_R, the weights' 1/6, the output scale
   float* __restrict__ dst = sino.at(b) + (size_t)j * P.n_s;
   const int2* tr = P.tau + ((size_t)m * P.n_own + o) * P.n_s;  // rho position of each sample
-  for (int k = threadIdx.x; k < P.n_s; k += blockDim.x) {
-    const int2 t = tr[k];
-    float w[4];
-    bspline_w6(__int_as_float(t.y), w);
-    const int kq = t.x;
-    float acc = 0.f;
+  row_copy(
+      P.n_s, [&](int k) { return tr[k]; },
+      [&](int k, int2 t) {
+        float w[4];
+        bspline_w6(__int_as_float(t.y), w);
+        const int kq = t.x;
+        float acc = 0.f;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) acc += w[a] * x[wrap1(kq - 1 + a, nr)];
-    dst[k] = acc * inv_aR;
-  }
+        for (int a = 0; a < 4; ++a) acc += w[a] * x[wrap1(kq - 1 + a, nr)];
+        dst[k] = acc * inv_aR;
+      });
 }
 
 rl_status launch_irfft_eval(const rl_plan* p, const float2* spec, Slices<float> sino, int batch, double scale,
