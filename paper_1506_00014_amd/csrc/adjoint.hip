@@ -146,7 +146,7 @@ __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : 
 constexpr int kAThreads = 512;  // threads of the adjoint splat
 constexpr int kARows = 128;     // rays listed per pass
 constexpr int kSegMin = 8;      // shortest segment (rho indices)
-constexpr int kRayGap = 8;      // rays of one lane group are kRayGap apart
+constexpr int kRayGap = 2;      // rays of one lane group are kRayGap apart (2, 4, 8, 16 timed: 2 fastest)
 constexpr int kASlots = kARows + kRayGap;  // ray slots per pass (groups padded to equal size)
 constexpr int kAHalo = 4;       // halo of the LDS tile: footprints reach 3 pixels before and 2 after,
                                 // one more on each side covers the range's rounding
@@ -807,6 +807,9 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
   __shared__ double2 rcs[kASlots];
   __shared__ __align__(16) float us[kUCap];  // coarse rows [cg0, cg0 + nur) x rho [wq4, wq4 + span)
   __shared__ double es[kECap];               // e^{rho_q} / (a_R dx) for q in [wq4, wq4 + span)
+  // slot of each segment of the pass (a pass has at most kAThreads segments: the builder picks
+  // the segment length so that every thread walks at most one)
+  __shared__ short segslot[kAThreads];
   const int n = P.n, r = P.r;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
   const int b = blockIdx.z;
@@ -841,6 +844,15 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
       rpre[nslot] = nfull;
       rppre[nslot] = total - nfull;
     }
+    __syncthreads();
+    // segment -> slot: slot sl holds full segments rpre[sl] .. rpre[sl + 1] - 1 and, if
+    // rppre[sl + 1] > rppre[sl], the shorter segment nfull + rppre[sl]
+    for (int sl = threadIdx.x; sl < nslot; sl += blockDim.x) {
+      const int f1 = min(rpre[sl + 1], kAThreads);
+      for (int j = rpre[sl]; j < f1; ++j) segslot[j] = (short)sl;
+      if (rppre[sl + 1] > rppre[sl] && nfull + rppre[sl] < kAThreads) segslot[nfull + rppre[sl]] = (short)sl;
+    }
+    // (the barrier before the first window's walk publishes segslot)
     // rho windows of the row copies; a window starts at a multiple of 4 and spans a multiple
     // of 4, so rows are copied as float4 (n_rho is a multiple of 4).  The branch-free walk
     // reads an interleaved copy [rho][row] of the rows rlo .. rhi, which covers every ray's rows
@@ -903,18 +915,11 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
       }
       __syncthreads();
       // walk whole segments (clipped to the window)
-      for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        // segments [0, nfull) are full ones, the rest the shorter last ones of their rays;
-        // the slot holding segment j of its kind: the last k with prefix[k] <= j
+      for (int idx = threadIdx.x; idx < min(total, kAThreads); idx += blockDim.x) {
+        // segments [0, nfull) are full ones, the rest the shorter last ones of their rays
         const bool full = idx < nfull;
         const int j = full ? idx : idx - nfull;
-        int lo = 0, hi = nslot - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if ((full ? rpre[mid] : rppre[mid]) <= j) lo = mid;
-          else hi = mid - 1;
-        }
-        const int k = lo;
+        const int k = segslot[idx];
         const int q0 = rq0[k] + (full ? j - rpre[k] : rpre[k + 1] - rpre[k]) * seglen;
         if (BF) {
           SegWalk2 sw;
@@ -1025,50 +1030,38 @@ __global__ __launch_bounds__(kThreads) void k_ramp(DevPlan P, const float* __res
   fft_lds<kRowVals, false>(sh, ncr, 1, P.twp_ramp);
   const int step = P.tw_len / P.lr;
   const float* mult = P.ramp + (size_t)filter * (ncr + 1);
-  const int half = ncr / 2;
-  // forward packing -> X[k], X[km] (w: the twiddle of kk)
-  auto post = [&](float2 za, float2 zb, float2 w) {
-    const float2 e = cscale(cadd(za, cconj(zb)), 0.5f);
-    const float2 o = cscale(csub(za, cconj(zb)), 0.5f);
-    const float2 t = cmul(w, o);
-    return make_float2(e.x + t.y, e.y - t.x);
-  };
-  // inverse packing from (Y[k], Y[km])
-  auto pre = [&](float2 ya, float2 yb, float2 w) {
-    const float2 bb = cconj(yb);
-    const float2 e = cadd(ya, bb), dd = csub(ya, bb);
-    const float2 oo = cmul(dd, cconj(w));
-    return make_float2(e.x - oo.y, e.y + oo.x);
-  };
-  for (int base = 0; base <= half; base += kChunk * (int)blockDim.x) {
-    float2 wk[kChunk], wm[kChunk];
-    float mk[kChunk], mm[kChunk];
-#pragma unroll
-    for (int c = 0; c < kChunk; ++c) {  // the chunk's twiddles and multipliers (global) first
-      const int k = min(base + (int)threadIdx.x + c * (int)blockDim.x, half);
-      const int km = ncr - k;
-      wk[c] = P.tw[k * step];
-      wm[c] = P.tw[km * step];
-      mk[c] = mult[k];
-      mm[c] = mult[km];
-    }
-#pragma unroll
-    for (int c = 0; c < kChunk; ++c) {
-      const int k = base + (int)threadIdx.x + c * (int)blockDim.x;
-      if (k > half) continue;
-      const int km = ncr - k;
-      const float2 a = sh[k];
-      const float2 bz = sh[k == 0 ? 0 : km];
-      const float2 Xk = cscale(post(a, bz, wk[c]), mk[c]);
-      const float2 Xm = cscale(post(bz, a, wm[c]), mm[c]);
-      const float2 Zk = pre(Xk, Xm, wk[c]);
-      if (k == 0) {
-        sh[0] = Zk;
-      } else {
-        const float2 Zm = pre(Xm, Xk, wm[c]);
-        sh[k] = Zk;
-        sh[km] = Zm;
-      }
+  for (int k = threadIdx.x; k <= ncr / 2; k += blockDim.x) {
+    const int km = ncr - k;
+    const float2 a = sh[k];
+    const float2 bz = sh[k == 0 ? 0 : km];
+    // forward packing -> X[k], X[km]
+    auto post = [&](float2 za, float2 zb, int kk) {
+      const float2 e = cscale(cadd(za, cconj(zb)), 0.5f);
+      const float2 o = cscale(csub(za, cconj(zb)), 0.5f);
+      const float2 w = P.tw[kk * step];
+      const float2 t = cmul(w, o);
+      return make_float2(e.x + t.y, e.y - t.x);
+    };
+    float2 Xk = post(a, bz, k);
+    float2 Xm = post(bz, a, km);
+    Xk = cscale(Xk, mult[k]);
+    Xm = cscale(Xm, mult[km]);
+    // inverse packing from (Y[k], Y[km])
+    auto pre = [&](float2 ya, float2 yb, int kk) {
+      const float2 bb = cconj(yb);
+      const float2 e = cadd(ya, bb), dd = csub(ya, bb);
+      float2 w = P.tw[kk * step];
+      w.y = -w.y;
+      const float2 oo = cmul(dd, w);
+      return make_float2(e.x - oo.y, e.y + oo.x);
+    };
+    const float2 Zk = pre(Xk, Xm, k);
+    if (k == 0) {
+      sh[0] = Zk;
+    } else {
+      const float2 Zm = pre(Xm, Xk, km);
+      sh[k] = Zk;
+      sh[km] = Zm;
     }
   }
   __syncthreads();

@@ -141,9 +141,10 @@ constexpr int kFQ = 64;         // rho indices per block: one per lane of a wave
 constexpr int kFRows = 8;       // coarse rows per block
 constexpr int kFPatch = 8448;   // floats of the LDS image patch (large tiles)
 constexpr int kFPatchSmall = 5504;  // patch of the small tiles: four blocks per CU fit in LDS
-// Row pitches of the two patches (odd, so that rows spread over the LDS banks).  A fixed pitch
-// puts the 16 taps of a sample at compile-time offsets from one address.  A box is staged when
-// its width fits the pitch and its height PATCH / PITCH rows.
+// Row pitches of the patches (odd, so that rows spread over the LDS banks).  A fixed pitch puts
+// the 16 taps of a sample at compile-time offsets from one address; a box is staged when its
+// width fits the pitch and its height PATCH / PITCH rows.  Pitch 0: the box's own width | 1
+// (boxes of wide sectors, M >= 6), staged when that pitch times its height fits PATCH.
 constexpr int kFPitch = 93;
 constexpr int kFPitchSmall = 77;
 constexpr int kFThreads = 512;  // threads per block
@@ -232,7 +233,8 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __r
   }
   if (threadIdx.x < kFQ) se[threadIdx.x] = q0 + (int)threadIdx.x <= qlast ? P.erho[q0 + threadIdx.x] : 0.0;
   const int Xlo = box.x, Ylo = box.y, W = box.z, H = box.w;
-  const bool staged = (W | 1) <= PITCH && H <= PATCH / PITCH;
+  const int pitch = PITCH ? PITCH : (W | 1);
+  const bool staged = PITCH ? ((W | 1) <= PITCH && H <= PATCH / PITCH) : pitch * H <= PATCH;
   {
     if (staged) {
       // groups of four consecutive pixels in flat order; (ly, lg) advance by the block stride
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __r
               }
               v[u] = make_float4(t[0], t[1], t[2], t[3]);
             }
-            dsti[u] = ly * PITCH + 4 * lg;
+            dsti[u] = ly * pitch + 4 * lg;
           }
           ly += dly;
           lg += dlg;
@@ -307,11 +309,11 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __r
       bspline_w6((float)(Y - fy), wy);
       const unsigned bx = min((unsigned)((int)fx - 1 - Xlo), (unsigned)(W - 4));
       const unsigned by = min((unsigned)((int)fy - 1 - Ylo), (unsigned)(H - 4));
-      const float* p0 = patch + __umul24(by, (unsigned)PITCH) + bx;
+      const float* p0 = patch + __umul24(by, (unsigned)pitch) + bx;
       float v = 0.f;
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
-        const float* pr = p0 + bb * PITCH;
+        const float* pr = p0 + bb * pitch;
         v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
       }
       const bool in = tl < nft && q <= qlast && q >= qr.x && q <= qr.y;
@@ -414,25 +416,32 @@ static size_t cart2lp_lds(const DevPlan& d, int patch) {
          kFQ * sizeof(double);
 }
 
-// The plan lists the tiles whose image box fits kFPatchSmall (and those with no sample in D)
-// first, then the others; each list runs with its own LDS size, so that the small tiles,
-// most of them, run four blocks per CU.
-// The timing hooks record the two launches as one k_cart2lp interval.
+// The plan lists the tiles whose image box fits the small patch at its pitch (and those with
+// no sample in D) first, then those that fit the large patch at its pitch, then the others;
+// each list runs with its own LDS size and pitch, so that the small tiles, most of them, run
+// four blocks per CU.  The timing hooks record the launches as one k_cart2lp interval.
 rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   const int slot = prof_open("k_cart2lp", s);
   rl_status st = RL_OK;
-  // with the split off, every tile runs with the large patch (one launch over both lists)
-  const int n_small = p->tune.fwd_patch_split ? d.ftiles_small : 0;
-  const int n_large = d.ftiles_small + d.ftiles_large - n_small;
+  // with the split off, every tile runs with the large patch at its box's pitch (one launch
+  // over the three lists)
+  const bool split = p->tune.fwd_patch_split != 0;
+  const int n_small = split ? d.ftiles_small : 0, n_mid = split ? d.ftiles_mid : 0;
+  const int n_large = d.ftiles_small + d.ftiles_mid + d.ftiles_large - n_small - n_mid;
   if (n_small > 0) {
     hipLaunchKernelGGL((k_cart2lp<kFPatchSmall, kFPitchSmall>), dim3(n_small, batch), dim3(kFThreads),
                        cart2lp_lds(d, kFPatchSmall), s, d, d.ftiles, c, u, p->tune.fwd_xcd_order);
     st = check_launch("k_cart2lp");
   }
+  if (st == RL_OK && n_mid > 0) {
+    hipLaunchKernelGGL((k_cart2lp<kFPatch, kFPitch>), dim3(n_mid, batch), dim3(kFThreads), cart2lp_lds(d, kFPatch),
+                       s, d, d.ftiles + n_small, c, u, p->tune.fwd_xcd_order);
+    st = check_launch("k_cart2lp");
+  }
   if (st == RL_OK && n_large > 0) {
-    hipLaunchKernelGGL((k_cart2lp<kFPatch, kFPitch>), dim3(n_large, batch), dim3(kFThreads),
-                       cart2lp_lds(d, kFPatch), s, d, d.ftiles + n_small, c, u, p->tune.fwd_xcd_order);
+    hipLaunchKernelGGL((k_cart2lp<kFPatch, 0>), dim3(n_large, batch), dim3(kFThreads), cart2lp_lds(d, kFPatch), s,
+                       d, d.ftiles + n_small + n_mid, c, u, p->tune.fwd_xcd_order);
     st = check_launch("k_cart2lp");
   }
   prof_close(slot, s);
@@ -440,14 +449,17 @@ rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, 
 }
 
 // Plan time (host): the tile lists of launch_cart2lp, from the image boxes.
-std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small) {
-  std::vector<int> small, large;
+std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small, int* n_mid) {
+  std::vector<int> small, mid, large;
   for (int t = 0; t < (int)boxes.size(); ++t) {
     const int4 bx = boxes[t];
     const bool fits_small = (bx.z | 1) <= kFPitchSmall && bx.w <= kFPatchSmall / kFPitchSmall;
-    ((bx.z == 0 || fits_small) ? small : large).push_back(t);
+    const bool fits_mid = (bx.z | 1) <= kFPitch && bx.w <= kFPatch / kFPitch;
+    ((bx.z == 0 || fits_small) ? small : fits_mid ? mid : large).push_back(t);
   }
   *n_small = (int)small.size();
+  *n_mid = (int)mid.size();
+  small.insert(small.end(), mid.begin(), mid.end());
   small.insert(small.end(), large.begin(), large.end());
   return small;
 }
@@ -637,6 +649,8 @@ rl_status prepare_forward_launches(const rl_plan* p) {
   if (st != RL_OK) return st;
   st = ensure_dyn_lds((const void*)k_cart2lp<kFPatch, kFPitch>, cart2lp_lds(p->d, kFPatch),
                       "hipFuncSetAttribute(k_cart2lp)");
+  if (st != RL_OK) return st;
+  st = ensure_dyn_lds((const void*)k_cart2lp<kFPatch, 0>, cart2lp_lds(p->d, kFPatch), "hipFuncSetAttribute(k_cart2lp)");
   if (st != RL_OK) return st;
   switch (p->d.k_theta) {
 #define RL_THETA_CASE(K, K1, K2) \

@@ -559,8 +559,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   }
 
   const std::vector<int4> fbox = build_fwd_boxes(d, fine_cs, fine_q, erho);
-  int n_small_tiles = 0;
-  const std::vector<int> ftiles = build_fwd_tiles(fbox, &n_small_tiles);
+  int n_small_tiles = 0, n_mid_tiles = 0;
+  const std::vector<int> ftiles = build_fwd_tiles(fbox, &n_small_tiles, &n_mid_tiles);
 
   // ---------------- kernel table: zeta_hat on the device in FP64
   const int nkt = g.k_theta / 2 + 1, nkr = g.n_rho / 2 + 1;
@@ -729,7 +729,8 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   d.fbox = (const int4*)(mem + o_fb);
   d.ftiles = (const int*)(mem + o_ft);
   d.ftiles_small = n_small_tiles;
-  d.ftiles_large = (int)ftiles.size() - n_small_tiles;
+  d.ftiles_mid = n_mid_tiles;
+  d.ftiles_large = (int)ftiles.size() - n_small_tiles - n_mid_tiles;
   hipLaunchKernelGGL(k_tau_table, dim3(n_own, M), dim3(256), 0, 0, d, (int2*)(mem + o_ta));
   if ((st = check_launch("k_tau_table")) != RL_OK) return cleanup(st);
   if ((st = check_hip(hipDeviceSynchronize(), "k_tau_table")) != RL_OK) return cleanup(st);

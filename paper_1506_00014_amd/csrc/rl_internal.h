@@ -65,7 +65,9 @@ struct DevPlan {
   const int4* fbox;        // [m][forward block rows][forward block columns] image box of each
                            // forward block: (x0, y0, width, height), width 0 if no sample in D
   const int* ftiles;       // forward tiles (indices into fbox): ftiles_small that fit the small
-  int ftiles_small, ftiles_large;  // patch (or have no sample in D), then the others
+                           // patch at its fixed pitch (or have no sample in D), ftiles_mid that
+                           // fit the large patch at its fixed pitch, then the others
+  int ftiles_small, ftiles_mid, ftiles_large;
   // splat passes of the adjoint (geometry only, built at plan time), see adjoint.hip
   int adj_ntx;             // tiles per image row
   const int* adj_off;      // [tiles + 1] first pass of each tile
@@ -153,7 +155,7 @@ constexpr int theta_k1(int k_theta) { return k_theta <= 32 ? k_theta : 32; }
 std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& cs,
                                   const std::vector<int2>& fq, const std::vector<double>& erho);
 // Plan time (host): the forward's tile lists (small-patch tiles first; their count in *n_small).
-std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small);
+std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small, int* n_mid);
 // The operator chains behind radon_fwd and radon_adj / radon_transpose / fbp (arguments
 // checked by the caller; ws holds workspace_layout(plan, batch, RL_OP_FWD or op)).
 rl_status forward_chain(const rl_plan* plan, Slices<const float> img, Slices<float> sino, int batch, void* ws,
