@@ -376,6 +376,13 @@ size_t rl_batch_workspace_bytes(const rl_batch* batch, rl_op op);
 rl_status rl_batch_fwd(const rl_batch* batch, void* d_ws, size_t ws_bytes, hipStream_t stream);
 rl_status rl_batch_adj(const rl_batch* batch, void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* d_imgs[i] = the paper's fast back-projection (sec. 5, Algorithm 2; radon_bp_lp) of
+ * d_sinos[i] for every slice, in the manner of rl_batch_adj (one batched call per plan, the
+ * plans' calls concurrent).  The workspace is rl_batch_workspace_bytes(batch, RL_OP_BP_LP).
+ * Errors: those of rl_batch_adj; RL_ERR_GEOMETRY if a plan has q_theta != 1 (nothing is
+ * launched). */
+rl_status rl_batch_bp_lp(const rl_batch* batch, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
 /* Release a batch (not its buffers or plans).  NULL is a no-op. */
 void rl_batch_destroy(rl_batch* batch);
 

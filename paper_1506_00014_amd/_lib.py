@@ -61,6 +61,7 @@ EXPORTED = (
     "rl_batch_workspace_bytes",
     "rl_batch_fwd",
     "rl_batch_adj",
+    "rl_batch_bp_lp",
     "rl_batch_destroy",
     "rl_em_norm",
     "rl_em",
@@ -169,7 +170,7 @@ def load(path: str = LIB_PATH):
     lib.rl_batch_create.restype = c_int32
     lib.rl_batch_workspace_bytes.argtypes = [c_void_p, c_int32]
     lib.rl_batch_workspace_bytes.restype = c_size_t
-    for name in ("rl_batch_fwd", "rl_batch_adj"):
+    for name in ("rl_batch_fwd", "rl_batch_adj", "rl_batch_bp_lp"):
         f = getattr(lib, name)
         f.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
         f.restype = c_int32

@@ -311,8 +311,9 @@ class RaggedBatch:
 
     items: list of (plan, image, sinogram) with image [n][n] and sinogram [n_theta][n_s]
     float32 CUDA tensors of that plan (contiguous).  forward() writes every sinogram from its
-    image (R), adjoint() every image from its sinogram (R#), each as one batched call per plan,
-    enqueued on the current stream; neither allocates, so both can be captured in a CUDA (HIP)
+    image (R), adjoint() every image from its sinogram (R#), bp_lp() every image by Algorithm 2
+    (plans with q_theta 1), each as one batched call per plan (the plans' calls concurrent),
+    enqueued on the current stream; none allocates, so each can be captured in a CUDA (HIP)
     graph and replayed after the tensors' contents change.  The tensors must stay alive.
     tune_cache: optional autotuner cache file; each plan's launch parameters for its slice count
     come from it or are tuned and appended (rl_batch_create).
@@ -347,7 +348,11 @@ class RaggedBatch:
             cache = None if tune_cache is None else str(tune_cache).encode()
             _lib.check("rl_batch_create", lib.rl_batch_create(c_plans, len(plans), c_of, c_imgs, c_sinos, n, cache,
                                                               ctypes.byref(self._ptr)))
-            nbytes = max(int(lib.rl_batch_workspace_bytes(self._ptr, op)) for op in (0, 1))
+            # R and R#, and Algorithm 2 if every plan allows it (q_theta 1)
+            ops = [_lib.RL_OP_FWD, _lib.RL_OP_ADJ]
+            if all(p.geom["q_theta"] == 1 for p in plans):
+                ops.append(_lib.RL_OP_BP_LP)
+            nbytes = max(int(lib.rl_batch_workspace_bytes(self._ptr, op)) for op in ops)
             self._ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
 
     def __del__(self):
@@ -366,4 +371,8 @@ class RaggedBatch:
 
     def adjoint(self):
         self._run(self._lib.rl_batch_adj, "rl_batch_adj")
+
+    def bp_lp(self):
+        """Every image from its sinogram by the paper's fast back-projection (Algorithm 2)."""
+        self._run(self._lib.rl_batch_bp_lp, "rl_batch_bp_lp")
 

@@ -35,27 +35,34 @@ size_t group_ws(const rl_batch::Group& g, rl_op op) {
   return (rl_workspace_bytes(g.plan, g.count, op) + 255) & ~(size_t)255;
 }
 
-// Run `op` on the group's slices as one batch, reading and writing the slices in place.
-rl_status run_group(const rl_batch* b, const rl_batch::Group& g, bool fwd, void* ws, hipStream_t s) {
+// Run `op` (RL_OP_FWD: R, RL_OP_ADJ: R#, RL_OP_BP_LP: Algorithm 2) on the group's slices as
+// one batch, reading and writing the slices in place.
+rl_status run_group(const rl_batch* b, const rl_batch::Group& g, rl_op op, void* ws, hipStream_t s) {
   float* const* img_tab = b->d_ptrs + g.first;
   float* const* sino_tab = b->d_ptrs + b->count + g.first;
-  if (fwd)
+  if (op == RL_OP_FWD)
     return forward_chain(g.plan, Slices<const float>{nullptr, img_tab, 0}, Slices<float>{nullptr, sino_tab, 0},
                          g.count, ws, -1, nullptr, s, 1.0);
+  if (op == RL_OP_BP_LP)
+    return bp_lp_chain(g.plan, Slices<const float>{nullptr, sino_tab, 0}, Slices<float>{nullptr, img_tab, 0}, g.count,
+                       ws, RL_OP_BP_LP, s);
   return adjoint_chain(g.plan, Slices<const float>{nullptr, sino_tab, 0}, Slices<float>{nullptr, img_tab, 0}, g.count,
                        ws, RL_OP_ADJ, false, s);
 }
 
-rl_status batch_run(const rl_batch* b, bool fwd, void* d_ws, size_t ws_bytes, hipStream_t s) {
+rl_status batch_run(const rl_batch* b, rl_op op, void* d_ws, size_t ws_bytes, hipStream_t s) {
   if (!b) return fail(RL_ERR_INVALID_ARG, "batch is NULL");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(RL_ERR_HIP, "hipGetDevice failed");
   if (dev != b->device) return fail(RL_ERR_INVALID_ARG, "batch was created on another device");
   if (b->count == 0) return RL_OK;
-  const size_t need = rl_batch_workspace_bytes(b, fwd ? RL_OP_FWD : RL_OP_ADJ);
+  if (op == RL_OP_BP_LP)
+    for (const auto& g : b->groups)
+      if (g.plan->d.q != 1)
+        return fail(RL_ERR_GEOMETRY, "rl_batch_bp_lp needs q_theta = 1 (its lattice rows are the sinogram rows)");
+  const size_t need = rl_batch_workspace_bytes(b, op);
   if (!d_ws || ws_bytes < need) return fail(RL_ERR_WORKSPACE, "workspace smaller than rl_batch_workspace_bytes");
   if (((uintptr_t)d_ws & 255) != 0) return fail(RL_ERR_WORKSPACE, "workspace is not 256-byte aligned");
-  const rl_op op = fwd ? RL_OP_FWD : RL_OP_ADJ;
   rl_status st = check_hip(hipEventRecord(b->fork, s), "hipEventRecord(batch fork)");
   size_t off = 0;
   for (size_t i = 0; i < b->groups.size() && st == RL_OK; ++i) {
@@ -63,7 +70,7 @@ rl_status batch_run(const rl_batch* b, bool fwd, void* d_ws, size_t ws_bytes, hi
     hipStream_t gs = b->streams[i];
     st = check_hip(hipStreamWaitEvent(gs, b->fork, 0), "hipStreamWaitEvent(batch fork)");
     if (st != RL_OK) break;
-    st = run_group(b, g, fwd, (char*)d_ws + off, gs);
+    st = run_group(b, g, op, (char*)d_ws + off, gs);
     // a chain that was forked is joined back even when one of its launches failed
     rl_status jt = check_hip(hipEventRecord(b->joins[i], gs), "hipEventRecord(batch join)");
     if (jt == RL_OK) jt = check_hip(hipStreamWaitEvent(s, b->joins[i], 0), "hipStreamWaitEvent(batch join)");
@@ -167,11 +174,15 @@ extern "C" size_t rl_batch_workspace_bytes(const rl_batch* batch, rl_op op) {
 }
 
 extern "C" rl_status rl_batch_fwd(const rl_batch* batch, void* d_ws, size_t ws_bytes, hipStream_t stream) {
-  return batch_run(batch, true, d_ws, ws_bytes, stream);
+  return batch_run(batch, RL_OP_FWD, d_ws, ws_bytes, stream);
 }
 
 extern "C" rl_status rl_batch_adj(const rl_batch* batch, void* d_ws, size_t ws_bytes, hipStream_t stream) {
-  return batch_run(batch, false, d_ws, ws_bytes, stream);
+  return batch_run(batch, RL_OP_ADJ, d_ws, ws_bytes, stream);
+}
+
+extern "C" rl_status rl_batch_bp_lp(const rl_batch* batch, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  return batch_run(batch, RL_OP_BP_LP, d_ws, ws_bytes, stream);
 }
 
 extern "C" void rl_batch_destroy(rl_batch* batch) {

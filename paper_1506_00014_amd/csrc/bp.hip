@@ -44,7 +44,7 @@ size_t bp_rows_lds(const DevPlan& d) {
 }  // namespace
 
 // Block: owned row o of one (slice, partition); writes the row's rho half-spectrum.
-__global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const float* __restrict__ sino,
+__global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, Slices<const float> sino,
                                                            float2* __restrict__ spec) {
   extern __shared__ float2 sh[];
   const int nc = P.nc, nr = P.n_rho, ns = P.n_s;
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const floa
   float* gs = x;                   // [nw] the sinogram row at index k + kBpPad, zeros outside
                                    // (dead once cs is built; x then takes its place)
   float* cs = x + max(nr, nw);     // [nw] its spline coefficients, same indexing
-  const float* src = sino + ((size_t)b * P.n_theta + j) * ns;
+  const float* __restrict__ src = sino.at(b) + (size_t)j * ns;
   row_copy(
       nw,
       [&](int i) { return src[min(max(i - kBpPad, 0), ns - 1)]; },
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, const floa
 // than kStageMin slices gain nothing from the staging and lose occupancy to its LDS.
 template <bool STAGED>
 __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* __restrict__ lat,
-                                                        float* __restrict__ img, int batch) {
+                                                        Slices<float> img, int batch) {
   __shared__ float box[STAGED ? kBch : 1][STAGED ? kBox : 1];
   __shared__ int red[2][4];  // per partition parity: min/max row base, min/max column base
   const int t = (int)threadIdx.x, wv = t >> 6, ln = t & 63;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* 
   if (in_img) {
 #pragma unroll
     for (int bb = 0; bb < kBch; ++bb)
-      if (bb < nb) img[((size_t)(b0 + bb) * P.n + iy) * P.n + ix] = acc[bb] * (1.0f / 36.0f);
+      if (bb < nb) img.at(b0 + bb)[(size_t)iy * P.n + ix] = acc[bb] * (1.0f / 36.0f);
   }
 }
 
@@ -254,8 +254,8 @@ rl_status prepare_bp_launches(const rl_plan* p) {
   return ensure_dyn_lds((const void*)k_bp_rows_rfft, bp_rows_lds(p->d), "hipFuncSetAttribute(k_bp_rows_rfft)");
 }
 
-static rl_status bp_lp_chain(const rl_plan* plan, const float* sino, float* img, int batch, void* ws, rl_op op,
-                             hipStream_t s) {
+rl_status bp_lp_chain(const rl_plan* plan, Slices<const float> sino, Slices<float> img, int batch, void* ws,
+                      rl_op op, hipStream_t s) {
   const DevPlan& d = plan->d;
   const WsLayout L = workspace_layout(plan, batch, op);
   char* w = (char*)ws;
@@ -290,7 +290,9 @@ extern "C" rl_status radon_bp_lp(const rl_plan* plan, const float* d_sino, float
     return fail(RL_ERR_GEOMETRY, "radon_bp_lp needs q_theta = 1 (its lattice rows are the sinogram rows)");
   rl_status st = adj_checks(plan, d_sino, d_img, batch, d_ws, ws_bytes, RL_OP_BP_LP);
   if (st != RL_OK || batch == 0) return st;
-  return bp_lp_chain(plan, d_sino, d_img, batch, d_ws, RL_OP_BP_LP, stream);
+  const DevPlan& d = plan->d;
+  return bp_lp_chain(plan, dense(d_sino, (size_t)d.n_theta * d.n_s), dense(d_img, (size_t)d.n * d.n), batch, d_ws,
+                     RL_OP_BP_LP, stream);
 }
 
 extern "C" rl_status fbp_lp(const rl_plan* plan, const float* d_sino, float* d_img, int32_t batch, rl_filter filter,
@@ -304,5 +306,7 @@ extern "C" rl_status fbp_lp(const rl_plan* plan, const float* d_sino, float* d_i
   const WsLayout L = workspace_layout(plan, batch, RL_OP_FBP_LP);
   float* wg = (float*)((char*)d_ws + L.off[4]);
   if ((st = launch_ramp(plan, d_sino, wg, batch, (int)filter, stream)) != RL_OK) return st;
-  return bp_lp_chain(plan, wg, d_img, batch, d_ws, RL_OP_FBP_LP, stream);
+  const DevPlan& d = plan->d;
+  return bp_lp_chain(plan, dense((const float*)wg, (size_t)d.n_theta * d.n_s), dense(d_img, (size_t)d.n * d.n), batch,
+                     d_ws, RL_OP_FBP_LP, stream);
 }

@@ -265,7 +265,7 @@ __device__ __forceinline__ void irfft_pre(float2* Z, int nc, const float2* __res
 // tw[n] = exp(-2 pi i n / tw_len) (tw_len a multiple of R).  A factor 3 is split off first
 // (decimation in time: three interleaved sub-transforms of length R/3, then radix-3
 // butterflies with twiddles w^{s k}); a power of two runs radix-2 decimation in time with a
-// compile-time bit reversal.
+// compile-time bit reversal, the twiddles 1 and -i (+i inverse) applied without a multiply.
 template <int R>
 constexpr int bitrev(int i) {
   int r = 0;
@@ -324,7 +324,7 @@ __device__ __forceinline__ void reg_fft(float2 (&v)[R], const float2* __restrict
       for (int k = 0; k < half; ++k) {
         const int e = k * (R / len);  // exponent in units of 1/R turns
         float2 w;
-        if (e == 0) {
+        if (e == 0 || 4 * e == R) {  // 1 and -i (+i inverse) need no multiply
           w = make_float2(1.f, 0.f);
         } else {
           w = tw[e * tstep];
@@ -333,7 +333,7 @@ __device__ __forceinline__ void reg_fft(float2 (&v)[R], const float2* __restrict
 #pragma unroll
         for (int i = 0; i < R; i += len) {
           const float2 a = v[i + k];
-          const float2 b = (e == 0) ? v[i + k + half] : cmul(v[i + k + half], w);
+          const float2 b = (e == 0) ? v[i + k + half] : (4 * e == R) ? mul_mi<INV>(v[i + k + half]) : cmul(v[i + k + half], w);
           v[i + k] = cadd(a, b);
           v[i + k + half] = csub(a, b);
         }

@@ -162,6 +162,10 @@ rl_status forward_chain(const rl_plan* plan, Slices<const float> img, Slices<flo
                         int stop_stage, float* stage_out, hipStream_t s, double out_scale);
 rl_status adjoint_chain(const rl_plan* plan, Slices<const float> sino, Slices<float> img, int batch, void* ws, rl_op op,
                         bool transpose, hipStream_t s);
+// Algorithm 2 (sec. 5): the lattice rows from the sinogram rows, the theta convolution with the
+// back-projection kernel, the inverse rho FFT, and the Cartesian gather summed over partitions.
+rl_status bp_lp_chain(const rl_plan* plan, Slices<const float> sino, Slices<float> img, int batch, void* ws,
+                      rl_op op, hipStream_t s);
 // Argument checks shared by the sinogram -> image entry points (op selects the workspace).
 rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int batch, void* ws, size_t ws_bytes,
                      rl_op op);

@@ -59,7 +59,30 @@ def test_ragged_matches_plain_calls(setup):
         assert err <= 1e-6  # FP64 LDS accumulation: summation order may differ
 
 
-@pytest.mark.parametrize("op", ["forward", "adjoint"])
+def test_ragged_bp_lp_matches_plain_calls(setup):
+    """Algorithm 2 over the ragged batch (one batched call per plan, the plans concurrent)
+    equals per-slice radon_bp_lp; a plan with q_theta = 2 is refused before anything runs."""
+    from paper_1506_00014_amd import RadonPlan, RaggedBatch, _lib
+
+    dev, plans = setup
+    items = make_items(dev, plans, 650)
+    batch = RaggedBatch(items)
+    batch.bp_lp()
+    torch.cuda.synchronize()
+    for plan, img, sino in items:
+        ref = plan.bp_lp(sino)
+        err = (img - ref).abs().max().item() / ref.abs().max().item()
+        assert err <= 1e-6, err
+    fine = RadonPlan(64, 90, 64, q_theta=2)
+    img = torch.zeros(64, 64, device=dev)
+    sino = torch.zeros(90, 64, device=dev)
+    b2 = RaggedBatch([(fine, img, sino)])
+    with pytest.raises(_lib.RadonLibError) as exc:
+        b2.bp_lp()
+    assert exc.value.status == _lib.RL_ERR_GEOMETRY
+
+
+@pytest.mark.parametrize("op", ["forward", "adjoint", "bp_lp"])
 def test_ragged_graph_replay(setup, op):
     """Capture one call of the batch (the plans' chains as parallel branches forked from and
     joined to the capturing stream), replay it after changing the inputs in place, with eager
@@ -96,7 +119,7 @@ def test_ragged_graph_replay(setup, op):
             if op == "forward":
                 assert torch.equal(sino, plan.forward(img))
             else:
-                ref = plan.adjoint(sino)
+                ref = plan.adjoint(sino) if op == "adjoint" else plan.bp_lp(sino)
                 assert (img - ref).abs().max().item() <= 1e-6 * ref.abs().max().item()
         _ = torch.ones(1000, device=dev).sum().item()  # eager work between replays
 
