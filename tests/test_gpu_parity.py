@@ -81,9 +81,14 @@ CASES = [
     (16, 24, 16, 4, {}),      # smaller than one tile
 ]
 
-# larger theta-FFT lengths (K = 512, 1024, 2048) and the 1024 x 1024 configuration
+# larger theta-FFT lengths (K = 512, 1024, 2048), the 1024 x 1024 configuration, wide sectors
 BIG_CASES = [
     (768, 768, 768, 4, {}),   # the odd size of the ragged-batch mix (N_rho 2048, K 512)
+    # wide forward sectors: M = 6 runs all three forward tile lists (small patch at pitch 77, large
+    # at pitch 93, large at each box's own pitch), M = 8 mostly the last, staged or gathering from
+    # global memory where even that does not fit
+    (768, 768, 768, 6, {}),
+    (768, 768, 768, 8, {}),
     (256, 1024, 256, 4, {}),
     (512, 2048, 512, 4, {}),
     (256, 4096, 256, 4, {}),
