@@ -555,10 +555,12 @@ __device__ __forceinline__ void splat_walk_fixed(const SegWalk2& sw, double* acc
 // k / kRayGap, ng = ceil(nrows / kRayGap); slots past the last ray are empty).  Header, three
 // int4: (m, sx, sy, nslot), (cg0, cg1, qlo, qhi), (seglen, segments, first slot record, full
 // segments); one int4 per slot: (t, first rho index, last rho index, first full segment |
-// first shorter segment << 16).  The kernel below
+// rank of its shorter segment << 16), the shorter segments numbered by decreasing length
+// after all full ones (kNoShort: the ray's range is a whole number of full ones).  The kernel below
 // computes them (one block per tile): COUNT only counts passes and slots per tile, WRITE
 // stores them at the offsets the host derives from the counts.
 constexpr int kBThreads = 256;  // threads of the pass builder (>= kASlots)
+constexpr int kNoShort = 0x7fff;  // slot record: the slot has no shorter segment
 
 template <bool WRITE>
 __global__ __launch_bounds__(kBThreads) void k_adj_build(DevPlan P, int2* __restrict__ counts,
@@ -568,6 +570,7 @@ __global__ __launch_bounds__(kBThreads) void k_adj_build(DevPlan P, int2* __rest
   __shared__ int rqb[kASlots];
   __shared__ int rpre[kASlots + 1];
   __shared__ int rpart[kASlots + 1];
+  __shared__ int rplen[kASlots];  // length of each slot's shorter segment (0: none)
   __shared__ int qext[4];
   const int n = P.n, r = P.r;
   const int tile = blockIdx.y * gridDim.x + blockIdx.x;
@@ -680,11 +683,13 @@ __global__ __launch_bounds__(kBThreads) void k_adj_build(DevPlan P, int2* __rest
             const int len = max(kSegMin, (ssum + (kAThreads - nray) - 1) / (kAThreads - nray));
             // a ray's range is cut into full segments of len samples and at most one shorter
             // one; the full segments of all rays are numbered first, so that the waves that
-            // walk them have no idle lanes
+            // walk them have no idle lanes, then the shorter ones by decreasing length, so that
+            // each wave of them walks segments of similar lengths
             for (int i = threadIdx.x; i < nslot; i += 64) {
               const int c = rpre[i];
               rpre[i] = c / len;
               rpart[i] = (c % len) != 0;
+              rplen[i] = c % len;
             }
             const int nfull = wave_exclusive_scan(rpre, nslot);
             const int npart = wave_exclusive_scan(rpart, nslot);
@@ -699,6 +704,21 @@ __global__ __launch_bounds__(kBThreads) void k_adj_build(DevPlan P, int2* __rest
           const int total = rpre[nslot] + rpart[nslot];
           if (total > 0) {  // uniform
             if (WRITE) {
+              // rank of each shorter segment: longer ones first, equal lengths in slot order
+              // (kNoShort: the slot has none); rpart is free again after the totals above
+              for (int sl = threadIdx.x; sl < nslot; sl += blockDim.x) {
+                const int pl = rplen[sl];
+                int rank = kNoShort;
+                if (pl > 0) {
+                  rank = 0;
+                  for (int j = 0; j < nslot; ++j) {
+                    const int pj = rplen[j];
+                    rank += pj > pl || (pj == pl && j < sl);
+                  }
+                }
+                rpart[sl] = rank;
+              }
+              __syncthreads();
               const int cg0 = max(floordiv(tc, r) - 1, 0);
               const int cg1 = min(floordiv(tc + nrows - 1, r) + 2, P.n_sup - 1);
               if (threadIdx.x == 0) {
@@ -800,7 +820,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
   __shared__ double acc[kAW * kAP];
   __shared__ int rq0[kASlots];
   __shared__ int rpre[kASlots + 1];   // first full segment of each slot
-  __shared__ int rppre[kASlots + 1];  // first shorter segment of each slot
+  __shared__ int rppre[kASlots];      // index of the slot's shorter segment among them
   __shared__ int rcnt[kASlots];
   __shared__ int rcg[kASlots];
   __shared__ float4 rdw[kASlots];
@@ -840,17 +860,14 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
       rcg[sl] = cg;
       rdw[sl] = P.dec[e.x - r * cg];
     }
-    if (threadIdx.x == 0) {
-      rpre[nslot] = nfull;
-      rppre[nslot] = total - nfull;
-    }
+    if (threadIdx.x == 0) rpre[nslot] = nfull;
     __syncthreads();
-    // segment -> slot: slot sl holds full segments rpre[sl] .. rpre[sl + 1] - 1 and, if
-    // rppre[sl + 1] > rppre[sl], the shorter segment nfull + rppre[sl]
+    // segment -> slot: slot sl holds full segments rpre[sl] .. rpre[sl + 1] - 1 and, unless
+    // rppre[sl] is kNoShort, the shorter segment nfull + rppre[sl]
     for (int sl = threadIdx.x; sl < nslot; sl += blockDim.x) {
       const int f1 = min(rpre[sl + 1], kAThreads);
       for (int j = rpre[sl]; j < f1; ++j) segslot[j] = (short)sl;
-      if (rppre[sl + 1] > rppre[sl] && nfull + rppre[sl] < kAThreads) segslot[nfull + rppre[sl]] = (short)sl;
+      if (rppre[sl] != kNoShort && nfull + rppre[sl] < kAThreads) segslot[nfull + rppre[sl]] = (short)sl;
     }
     // (the barrier before the first window's walk publishes segslot)
     // rho windows of the row copies; a window starts at a multiple of 4 and spans a multiple

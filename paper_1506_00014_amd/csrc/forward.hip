@@ -138,7 +138,8 @@ rl_status launch_prefilter(const rl_plan* p, Slices<const float> in, Slices<floa
 
 // ------------------------------------------------------------------ cart -> log-polar
 constexpr int kFQ = 64;         // rho indices per block: one per lane of a wave
-constexpr int kFRows = 8;       // coarse rows per block
+constexpr int kFRows = 8;       // coarse rows per segment (tile)
+constexpr int kFSeg = 2;        // segments (vertically adjacent tiles) per block
 constexpr int kFPatch = 8448;   // floats of the LDS image patch (large tiles)
 constexpr int kFPatchSmall = 5504;  // patch of the small tiles: four blocks per CU fit in LDS
 // Row pitches of the patches (odd, so that rows spread over the LDS banks).  A fixed pitch puts
@@ -169,12 +170,14 @@ __device__ __forceinline__ float bicubic_at(double X, double Y, int n, Tap tap) 
   return v * (1.0f / 36.0f);
 }
 
-// Block: kFQ consecutive rho indices and kFRows coarse rows of one (slice, partition).
-// 1) The fine rays feeding those rows sweep an annular sector of the image; its bounding box
-//    is staged in LDS (global gathers if it does not fit).  2) Each wave computes the bicubic
-//    samples of one fine ray at a time, a lane per rho index, into an LDS buffer; samples
-//    outside D are zero.  3) Each coarse sample is the decimation filter over the fine rows
-//    around it, times e^rho.
+// Block: kFQ consecutive rho indices and kFSeg x kFRows coarse rows of one (slice, partition),
+// taken as kFSeg segments of kFRows rows (each a tile with its own image box).  Per segment:
+// 1) The fine rays feeding its rows sweep an annular sector of the image; the sector's
+//    bounding box is staged in LDS (global gathers if it does not fit).  2) Each wave computes
+//    the bicubic samples of one fine ray at a time, a lane per rho index, into an LDS buffer;
+//    samples outside D are zero.  The last 3r - 1 fine rays of a segment are the first of the
+//    next: they are moved to the front of the buffer and not sampled again.  3) Each coarse
+//    sample is the decimation filter over the fine rows around it, times e^rho.
 template <int PATCH, int PITCH>
 __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __restrict__ tiles,
                                                         const float* __restrict__ c, float* __restrict__ u,
@@ -182,184 +185,233 @@ __global__ __launch_bounds__(kFThreads) void k_cart2lp(DevPlan P, const int* __r
   extern __shared__ float smem[];
   float* patch = smem;
   float* vbuf = smem + PATCH;
-  // tile (m, by, bx) from the plan's list for this patch size; slice from blockIdx.y
+  // first tile (m, by, bx) of the block from the plan's list for this patch size; slice from
+  // blockIdx.y
   const int gx = (P.n_rho + kFQ - 1) / kFQ, gy = (P.n_sup + kFRows - 1) / kFRows;
   // (list entry, slice) of this block; with xcd_order each XCD takes one contiguous run of
   // them, so tiles that read overlapping image boxes share that XCD's L2
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   const int lid = xcd_order ? xcd_block(bid, gridDim.x * gridDim.y) : bid;
   const int b = lid / gridDim.x;
-  const int tile = tiles[lid - b * gridDim.x];
-  const int bx = tile % gx, by = (tile / gx) % gy, m = tile / (gx * gy);
+  const int tile0 = tiles[lid - b * gridDim.x];
+  const int bx = tile0 % gx, by0 = (tile0 / gx) % gy, m = tile0 / (gx * gy);
   const int bm = b * P.m + m;
   const int q0 = bx * kFQ;
-  const int i0 = by * kFRows;
-  const int i1 = min(i0 + kFRows, P.n_sup);
   const int n = P.n, r = P.r;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const double X0 = P.X0[m], Y0 = P.Y0[m];
   const float* img = c + (size_t)b * n * n;
   const double2* cs = P.fine_cs + (size_t)m * P.n_fine;
   const int2* fq = P.fine_q + (size_t)m * P.n_fine;
-  // fine rows t with |t - r i| < 2r for some i in [i0, i1)
-  const int tlo = r * (i0 - 2) + 1, thi = r * (i1 + 1) - 1;
-  const int nft = thi - tlo + 1;
   const int nftmax = r * (kFRows + 3) - 1;  // the launch sizes LDS for this many rows
-  // LDS copies of the block's ray table (direction, rho range inside D) and of e^rho
+  // LDS copies of the segment's ray table (direction, rho range inside D), of e^rho and of the
+  // decimation taps
   double2* scs = reinterpret_cast<double2*>(vbuf + nftmax * kFQ);
   int2* sfq = reinterpret_cast<int2*>(scs + nftmax);
   double* se = reinterpret_cast<double*>(sfq + nftmax);
-  const int tclo = max(tlo, P.t_min), tchi = min(thi, P.t_min + P.n_fine - 1);
+  float* sdt = reinterpret_cast<float*>(se + kFQ);
   const int qlast = min(q0 + kFQ, P.n_rho) - 1;
-  // image box of the block's samples, built with the plan (W == 0: no sample inside D)
-  const int4 box = P.fbox[tile];
-  if (box.z == 0) {
-    for (int o = threadIdx.x; o < (i1 - i0) * kFQ; o += blockDim.x) {
-      const int il = o / kFQ, ql = o - il * kFQ;
-      if (q0 + ql <= qlast) u[((size_t)bm * P.n_sup + i0 + il) * P.n_rho + q0 + ql] = 0.f;
-    }
-    return;  // uniform across the block
-  }
-  for (int tl = threadIdx.x; tl < nft; tl += blockDim.x) {
-    const int t = tlo + tl;
-    int2 qr = make_int2(1, 0);  // empty
-    double2 tc = make_double2(0.0, 0.0);
-    if (t >= tclo && t <= tchi) {
-      qr = fq[t - P.t_min];
-      tc = cs[t - P.t_min];
-    }
-    sfq[tl] = qr;
-    scs[tl] = tc;
-  }
+  const int nd = 4 * r - 1, nd8 = (nd + 7) & ~7;  // taps, padded with zeros to chunks of 8
   if (threadIdx.x < kFQ) se[threadIdx.x] = q0 + (int)threadIdx.x <= qlast ? P.erho[q0 + threadIdx.x] : 0.0;
-  const int Xlo = box.x, Ylo = box.y, W = box.z, H = box.w;
-  const int pitch = PITCH ? PITCH : (W | 1);
-  const bool staged = PITCH ? ((W | 1) <= PITCH && H <= PATCH / PITCH) : pitch * H <= PATCH;
-  {
+  for (int k = threadIdx.x; k < nd8; k += blockDim.x) sdt[k] = k < nd ? P.dtap[k] : 0.f;
+  const int ql = lane, q = q0 + lane;
+  int kept = 0;  // leading fine rows of vbuf carried over from the previous segment
+  // image boxes of the block's tiles (built with the plan; W == 0: no sample inside D), all
+  // loaded up front
+  int4 boxes[kFSeg];
+#pragma unroll
+  for (int sg = 0; sg < kFSeg; ++sg) boxes[sg] = P.fbox[tile0 + min(sg, gy - 1 - by0) * gx];
+#pragma unroll
+  for (int sg = 0; sg < kFSeg; ++sg) {
+    const int by = by0 + sg;
+    if (by >= gy) break;  // uniform
+    const int i0 = by * kFRows;
+    const int i1 = min(i0 + kFRows, P.n_sup);
+    // fine rows t with |t - r i| < 2r for some i in [i0, i1)
+    const int tlo = r * (i0 - 2) + 1, thi = r * (i1 + 1) - 1;
+    const int nft = thi - tlo + 1;
+    const int tclo = max(tlo, P.t_min), tchi = min(thi, P.t_min + P.n_fine - 1);
+    const int4 box = boxes[sg];
+    if (sg > 0) __syncthreads();  // the previous segment is done with vbuf, the tables and the patch
+    if (box.z == 0) {
+      for (int o = threadIdx.x; o < (i1 - i0) * kFQ; o += blockDim.x) {
+        const int il = o / kFQ, ql2 = o - il * kFQ;
+        if (q0 + ql2 <= qlast) u[((size_t)bm * P.n_sup + i0 + il) * P.n_rho + q0 + ql2] = 0.f;
+      }
+      kept = 0;
+      continue;  // uniform across the block
+    }
+    // the previous segment's fine rows from r kFRows on are this segment's first `kept` rows
+    // (source rows start past the destination's end: no thread overwrites what another reads)
+    for (int o = threadIdx.x; o < kept * kFQ; o += blockDim.x) vbuf[o] = vbuf[r * kFRows * kFQ + o];
+    // one memory round trip for the segment's inputs: a ray-table entry per thread (address
+    // clamped into the table) and every staged group are loaded, unconditionally, before any
+    // is stored (a load under a branch would make the branch's join wait for it)
+    const int tq = min(max(tlo + (int)threadIdx.x, P.t_min), P.t_min + P.n_fine - 1) - P.t_min;
+    const int2 qr_ld = fq[tq];
+    const double2 tc_ld = cs[tq];
+    const int Xlo = box.x, Ylo = box.y, W = box.z, H = box.w;
+    const int pitch = PITCH ? PITCH : (W | 1);
+    const bool staged = PITCH ? ((W | 1) <= PITCH && H <= PATCH / PITCH) : pitch * H <= PATCH;
+    // groups of four consecutive pixels in flat order, at most PATCH / 4 of them: kU per thread;
+    // (ly, lg) advance by the block stride without a division per group.  A group inside the
+    // image is one float4 load (rows of 4-aligned groups are 16-byte aligned when n % 4 == 0);
+    // a group across the image edge is loaded again below, pixel by pixel with the periodic wrap
+    constexpr int kU = (PATCH / 4 + kFThreads - 1) / kFThreads;
+    const int Wg = W >> 2, tot = staged ? Wg * H : 0;
+    const bool vec_ok = (n & 3) == 0;
+    float4 v[kU];
+    int dsti[kU];
+    bool edge[kU];
+    {
+      const int wg = max(Wg, 1);
+      const int dly = (int)blockDim.x / wg, dlg = (int)blockDim.x - dly * wg;
+      int ly = (int)threadIdx.x / wg, lg = (int)threadIdx.x - ly * wg;
+#pragma unroll
+      for (int uu = 0; uu < kU; ++uu) {
+        const bool ok = uu * (int)blockDim.x + (int)threadIdx.x < tot;
+        int gyy = Ylo + ly;
+        if (gyy < 0 || gyy >= n) gyy = ((gyy % n) + n) % n;
+        const int gxx = Xlo + 4 * lg;
+        const bool inb = vec_ok && gxx >= 0 && gxx + 3 < n;
+        if (vec_ok && staged) {
+          const int xc = min(max(gxx, 0), n - 4);
+          v[uu] = *reinterpret_cast<const float4*>(img + (size_t)(ok ? gyy : 0) * n + xc);
+        }
+        dsti[uu] = ok ? ly * pitch + 4 * lg : -1;
+        edge[uu] = ok && !inb;
+        ly += dly;
+        lg += dlg;
+        if (lg >= wg) {
+          lg -= wg;
+          ++ly;
+        }
+      }
+    }
+    for (int tl = threadIdx.x; tl < nft; tl += blockDim.x) {
+      const int t = tlo + tl;
+      const bool in = t >= tclo && t <= tchi;
+      int2 qr = make_int2(1, 0);  // empty
+      double2 tc = make_double2(0.0, 0.0);
+      if (tl == (int)threadIdx.x) {
+        if (in) {
+          qr = qr_ld;
+          tc = tc_ld;
+        }
+      } else if (in) {  // rows past the block's threads (r > 46 only)
+        qr = fq[t - P.t_min];
+        tc = cs[t - P.t_min];
+      }
+      sfq[tl] = qr;
+      scs[tl] = tc;
+    }
+#pragma unroll
+    for (int uu = 0; uu < kU; ++uu) {
+      if (dsti[uu] < 0) continue;
+      float4 w = v[uu];
+      if (edge[uu]) {
+        const int idx = uu * (int)blockDim.x + (int)threadIdx.x;
+        const int ly = idx / Wg, lg = idx - ly * Wg;
+        int gyy = Ylo + ly;
+        if (gyy < 0 || gyy >= n) gyy = ((gyy % n) + n) % n;
+        const float* srow = img + (size_t)gyy * n;
+        float tt[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int x = Xlo + 4 * lg + e;
+          if (x < 0 || x >= n) x = ((x % n) + n) % n;
+          tt[e] = srow[x];
+        }
+        w = make_float4(tt[0], tt[1], tt[2], tt[3]);
+      }
+      float* d = patch + dsti[uu];
+      d[0] = w.x;
+      d[1] = w.y;
+      d[2] = w.z;
+      d[3] = w.w;
+    }
+    __syncthreads();
+    // fine samples of rows kept .. nft - 1: a wave takes one ray at a time (its table entries
+    // are wave-uniform LDS broadcasts), lane l the rho index q0 + l
+    const double E = se[ql];
     if (staged) {
-      // groups of four consecutive pixels in flat order; (ly, lg) advance by the block stride
-      // without a division per group; a group inside the image is one float4 load (rows of
-      // 4-aligned groups are 16-byte aligned when n % 4 == 0), a group across the image edge
-      // wraps pixel by pixel
-      const int Wg = W >> 2, tot = Wg * H;
-      const int dly = (int)blockDim.x / Wg, dlg = (int)blockDim.x - dly * Wg;
-      int ly = (int)threadIdx.x / Wg, lg = (int)threadIdx.x - ly * Wg;
-      const bool vec_ok = (n & 3) == 0;
-      for (int base = 0; base < tot; base += 2 * (int)blockDim.x) {
-        float4 v[2];
-        int dsti[2];
+      // two rays per step, branch-free (independent chains for the scheduler): taps are clamped
+      // into the patch and samples outside D or past the last ray are zeroed by a select
+      auto sample = [&](int tl) -> float {
+        const int tr = min(tl, nft - 1);
+        const int2 qr = sfq[tr];
+        const double2 tc = scs[tr];
+        const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
+        const double fx = floor(X), fy = floor(Y);
+        float wx[4], wy[4];
+        bspline_w6((float)(X - fx), wx);
+        bspline_w6((float)(Y - fy), wy);
+        const unsigned bxx = min((unsigned)((int)fx - 1 - Xlo), (unsigned)(W - 4));
+        const unsigned byy = min((unsigned)((int)fy - 1 - Ylo), (unsigned)(H - 4));
+        const float* p0 = patch + __umul24(byy, (unsigned)pitch) + bxx;
+        float v = 0.f;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
-          dsti[u] = -1;
-          if (idx < tot) {
-            int gy = Ylo + ly;
-            if (gy < 0 || gy >= n) gy = ((gy % n) + n) % n;
-            const float* srow = img + (size_t)gy * n;
-            const int gx = Xlo + 4 * lg;
-            if (vec_ok && gx >= 0 && gx + 3 < n) {
-              v[u] = *reinterpret_cast<const float4*>(srow + gx);
-            } else {
-              float t[4];
+        for (int bb = 0; bb < 4; ++bb) {
+          const float* pr = p0 + bb * pitch;
+          v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
+        }
+        const bool in = tl < nft && q <= qlast && q >= qr.x && q <= qr.y;
+        return in ? v * (1.0f / 36.0f) : 0.f;
+      };
+      for (int tl = kept + wave; tl < nft; tl += 2 * nwave) {
+        const float v0 = sample(tl);
+        const float v1 = sample(tl + nwave);
+        vbuf[tl * kFQ + ql] = v0;
+        if (tl + nwave < nft) vbuf[(tl + nwave) * kFQ + ql] = v1;
+      }
+    } else {
+      for (int tl = kept + wave; tl < nft; tl += nwave) {
+        const int2 qr = sfq[tl];
+        const double2 tc = scs[tl];
+        float v = 0.f;
+        if (q <= qlast && q >= qr.x && q <= qr.y) {
+          const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
+          v = bicubic_at(X, Y, n, [&](int x, int y) { return img[(size_t)wrap1(y, n) * n + wrap1(x, n)]; });
+        }
+        vbuf[tl * kFQ + ql] = v;
+      }
+    }
+    __syncthreads();
+    // decimation: u[i][q] = e^rho_q sum_n d_n v[r i + n][q], the taps in chunks of 8 whose 16 LDS
+    // reads all issue before the chunk's adds (past the last tap: row clamped, tap 0)
+    for (int o = threadIdx.x; o < (i1 - i0) * kFQ; o += blockDim.x) {
+      const int il = o / kFQ, ql2 = o - il * kFQ;
+      const int qq = q0 + ql2;
+      if (qq > qlast) continue;
+      const int i = i0 + il;
+      const float* vcol = vbuf + (r * i - (2 * r - 1) - tlo) * kFQ + ql2;
+      float acc = 0.f;
+      for (int k0 = 0; k0 < nd; k0 += 8) {
+        float tv[8], vv[8];
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                int x = gx + e;
-                if (x < 0 || x >= n) x = ((x % n) + n) % n;
-                t[e] = srow[x];
-              }
-              v[u] = make_float4(t[0], t[1], t[2], t[3]);
-            }
-            dsti[u] = ly * pitch + 4 * lg;
-          }
-          ly += dly;
-          lg += dlg;
-          if (lg >= Wg) {
-            lg -= Wg;
-            ++ly;
-          }
+        for (int j = 0; j < 8; ++j) {
+          tv[j] = sdt[k0 + j];
+          vv[j] = vcol[min(k0 + j, nd - 1) * kFQ];
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-          if (dsti[u] >= 0) {
-            float* d = patch + dsti[u];
-            d[0] = v[u].x;
-            d[1] = v[u].y;
-            d[2] = v[u].z;
-            d[3] = v[u].w;
-          }
+        for (int j = 0; j < 8; ++j) acc += tv[j] * vv[j];
       }
+      const float er = (float)(se[ql2] * (P.a_R * P.dx));
+      // lattice rows past this partition's support (partitions own different numbers of rows)
+      // are zero: the theta convolution must not see the fine rays beyond its last halo row
+      u[((size_t)bm * P.n_sup + i) * P.n_rho + qq] = i < P.sup_rows[m] ? acc * er : 0.f;
     }
-  }
-  __syncthreads();
-  // fine samples: a wave takes one ray at a time (its table entries are wave-uniform LDS
-  // broadcasts), lane l the rho index q0 + l
-  const int ql = lane, q = q0 + lane;
-  const double E = se[ql];
-  if (staged) {
-    // two rays per step, branch-free (independent chains for the scheduler): taps are clamped
-    // into the patch and samples outside D or past the last ray are zeroed by a select
-    auto sample = [&](int tl) -> float {
-      const int tr = min(tl, nft - 1);
-      const int2 qr = sfq[tr];
-      const double2 tc = scs[tr];
-      const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
-      const double fx = floor(X), fy = floor(Y);
-      float wx[4], wy[4];
-      bspline_w6((float)(X - fx), wx);
-      bspline_w6((float)(Y - fy), wy);
-      const unsigned bx = min((unsigned)((int)fx - 1 - Xlo), (unsigned)(W - 4));
-      const unsigned by = min((unsigned)((int)fy - 1 - Ylo), (unsigned)(H - 4));
-      const float* p0 = patch + __umul24(by, (unsigned)pitch) + bx;
-      float v = 0.f;
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        const float* pr = p0 + bb * pitch;
-        v += wy[bb] * (wx[0] * pr[0] + wx[1] * pr[1] + wx[2] * pr[2] + wx[3] * pr[3]);
-      }
-      const bool in = tl < nft && q <= qlast && q >= qr.x && q <= qr.y;
-      return in ? v * (1.0f / 36.0f) : 0.f;
-    };
-    for (int tl = wave; tl < nft; tl += 2 * nwave) {
-      const float v0 = sample(tl);
-      const float v1 = sample(tl + nwave);
-      vbuf[tl * kFQ + ql] = v0;
-      if (tl + nwave < nft) vbuf[(tl + nwave) * kFQ + ql] = v1;
-    }
-  } else {
-    for (int tl = wave; tl < nft; tl += nwave) {
-      const int2 qr = sfq[tl];
-      const double2 tc = scs[tl];
-      float v = 0.f;
-      if (q <= qlast && q >= qr.x && q <= qr.y) {
-        const double X = X0 + E * tc.x, Y = Y0 + E * tc.y;
-        v = bicubic_at(X, Y, n, [&](int x, int y) { return img[(size_t)wrap1(y, n) * n + wrap1(x, n)]; });
-      }
-      vbuf[tl * kFQ + ql] = v;
-    }
-  }
-  __syncthreads();
-  // decimation: u[i][q] = e^rho_q sum_n d_n v[r i + n][q]
-  const int nd = 4 * r - 1;
-  for (int o = threadIdx.x; o < (i1 - i0) * kFQ; o += blockDim.x) {
-    const int il = o / kFQ, ql = o - il * kFQ;
-    const int q = q0 + ql;
-    if (q > qlast) continue;
-    const int i = i0 + il;
-    const float* vcol = vbuf + (r * i - (2 * r - 1) - tlo) * kFQ + ql;
-    float acc = 0.f;
-    for (int k = 0; k < nd; ++k) acc += P.dtap[k] * vcol[k * kFQ];
-    const float er = (float)(P.erho[q] * (P.a_R * P.dx));
-    // lattice rows past this partition's support (partitions own different numbers of rows) are
-    // zero: the theta convolution must not see the fine rays beyond its last halo row
-    u[((size_t)bm * P.n_sup + i) * P.n_rho + q] = i < P.sup_rows[m] ? acc * er : 0.f;
+    // a full segment's rows r kFRows .. nft - 1 are the next segment's first 3r - 1
+    kept = i1 - i0 == kFRows ? 3 * r - 1 : 0;
   }
 }
 
-// Image boxes of the forward blocks (plan time, host): for block (bx, by) of partition m,
-// (Xlo, Ylo, W, H) bounds the image indices of every 4 x 4 tap set of its fine samples inside
-// D: the annular sector swept by its rays between e^rho of its first and last rho index,
-// widened where the outer arc crosses an axis direction, plus the taps' reach.  Xlo and W are
-// multiples of 4 (float4 staging).  W = 0 marks a block none of whose samples lies in D.
+// Image boxes of the forward tiles (plan time, host): for tile (bx, by) of partition m (kFQ rho
+// indices, kFRows coarse rows), (Xlo, Ylo, W, H) bounds the image indices of every 4 x 4 tap
+// set of its fine samples inside D: the annular sector swept by its rays between e^rho of its
+// first and last rho index, widened where the outer arc crosses an axis direction, plus the
+// taps' reach.  Xlo and W are multiples of 4 (float4 staging).  W = 0 marks a tile none of
+// whose samples lies in D.
 std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& cs_all,
                                   const std::vector<int2>& fq_all, const std::vector<double>& erho) {
   const int gx = (d.n_rho + kFQ - 1) / kFQ, gy = (d.n_sup + kFRows - 1) / kFRows, r = d.r;
@@ -413,13 +465,13 @@ std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& 
 static size_t cart2lp_lds(const DevPlan& d, int patch) {
   const int nft = d.r * (kFRows + 3) - 1;
   return (size_t)(patch + nft * kFQ) * sizeof(float) + (size_t)nft * (sizeof(double2) + sizeof(int2)) +
-         kFQ * sizeof(double);
+         kFQ * sizeof(double) + (size_t)((4 * d.r - 1 + 7) & ~7) * sizeof(float);
 }
 
-// The plan lists the tiles whose image box fits the small patch at its pitch (and those with
+// The plan lists the blocks whose tiles' image boxes fit the small patch at its pitch (or have
 // no sample in D) first, then those that fit the large patch at its pitch, then the others;
-// each list runs with its own LDS size and pitch, so that the small tiles, most of them, run
-// four blocks per CU.  The timing hooks record the launches as one k_cart2lp interval.
+// each list runs with its own LDS size and pitch, so that the small blocks, most of them, run
+// four per CU.  The timing hooks record the launches as one k_cart2lp interval.
 rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, hipStream_t s) {
   const DevPlan& d = p->d;
   const int slot = prof_open("k_cart2lp", s);
@@ -448,20 +500,31 @@ rl_status launch_cart2lp(const rl_plan* p, const float* c, float* u, int batch, 
   return st;
 }
 
-// Plan time (host): the tile lists of launch_cart2lp, from the image boxes.
-std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small, int* n_mid) {
-  std::vector<int> small, mid, large;
-  for (int t = 0; t < (int)boxes.size(); ++t) {
-    const int4 bx = boxes[t];
-    const bool fits_small = (bx.z | 1) <= kFPitchSmall && bx.w <= kFPatchSmall / kFPitchSmall;
-    const bool fits_mid = (bx.z | 1) <= kFPitch && bx.w <= kFPatch / kFPitch;
-    ((bx.z == 0 || fits_small) ? small : fits_mid ? mid : large).push_back(t);
-  }
-  *n_small = (int)small.size();
-  *n_mid = (int)mid.size();
-  small.insert(small.end(), mid.begin(), mid.end());
-  small.insert(small.end(), large.begin(), large.end());
-  return small;
+// Plan time (host): the block lists of launch_cart2lp, from the image boxes.  A block takes the
+// tiles (m, by, bx) .. (m, by + kFSeg - 1, bx) with by a multiple of kFSeg (fewer at the last
+// block row); it is listed, by its first tile, under the largest patch one of its tiles needs.
+std::vector<int> build_fwd_tiles(const DevPlan& d, const std::vector<int4>& boxes, int* n_small, int* n_mid) {
+  const int gx = (d.n_rho + kFQ - 1) / kFQ, gy = (d.n_sup + kFRows - 1) / kFRows;
+  std::vector<int> lists[3];
+  for (int m = 0; m < d.m; ++m)
+    for (int by = 0; by < gy; by += kFSeg)
+      for (int bx = 0; bx < gx; ++bx) {
+        const int t0 = (m * gy + by) * gx + bx;
+        int cls = 0;
+        for (int s = 0; s < kFSeg && by + s < gy; ++s) {
+          const int4 bb = boxes[t0 + s * gx];
+          const bool fits_small = (bb.z | 1) <= kFPitchSmall && bb.w <= kFPatchSmall / kFPitchSmall;
+          const bool fits_mid = (bb.z | 1) <= kFPitch && bb.w <= kFPatch / kFPitch;
+          cls = std::max(cls, (bb.z == 0 || fits_small) ? 0 : fits_mid ? 1 : 2);
+        }
+        lists[cls].push_back(t0);
+      }
+  *n_small = (int)lists[0].size();
+  *n_mid = (int)lists[1].size();
+  std::vector<int> out = lists[0];
+  out.insert(out.end(), lists[1].begin(), lists[1].end());
+  out.insert(out.end(), lists[2].begin(), lists[2].end());
+  return out;
 }
 
 // ------------------------------------------------------------------ rho FFTs of rows

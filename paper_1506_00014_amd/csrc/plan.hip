@@ -560,7 +560,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
 
   const std::vector<int4> fbox = build_fwd_boxes(d, fine_cs, fine_q, erho);
   int n_small_tiles = 0, n_mid_tiles = 0;
-  const std::vector<int> ftiles = build_fwd_tiles(fbox, &n_small_tiles, &n_mid_tiles);
+  const std::vector<int> ftiles = build_fwd_tiles(d, fbox, &n_small_tiles, &n_mid_tiles);
 
   // ---------------- kernel table: zeta_hat on the device in FP64
   const int nkt = g.k_theta / 2 + 1, nkr = g.n_rho / 2 + 1;

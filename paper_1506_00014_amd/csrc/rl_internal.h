@@ -62,17 +62,18 @@ struct DevPlan {
   const int2* tau;         // [m][n_own][n_s] rho position tau of S_m(theta_j, s_k) on each owned
                            // row: (floor(tau) clamped to [-1, n_rho], bits of the FP32 fraction)
   const float* dtap;       // [4r - 1] decimation taps d_n, n = -(2r-1) .. 2r-1
-  const int4* fbox;        // [m][forward block rows][forward block columns] image box of each
-                           // forward block: (x0, y0, width, height), width 0 if no sample in D
-  const int* ftiles;       // forward tiles (indices into fbox): ftiles_small that fit the small
-                           // patch at its fixed pitch (or have no sample in D), ftiles_mid that
-                           // fit the large patch at its fixed pitch, then the others
+  const int4* fbox;        // [m][forward tile rows][forward tile columns] image box of each
+                           // forward tile: (x0, y0, width, height), width 0 if no sample in D
+  const int* ftiles;       // forward blocks (index into fbox of each block's first tile):
+                           // ftiles_small whose tiles fit the small patch at its fixed pitch (or
+                           // have no sample in D), ftiles_mid that fit the large patch at its
+                           // fixed pitch, then the others
   int ftiles_small, ftiles_mid, ftiles_large;
   // splat passes of the adjoint (geometry only, built at plan time), see adjoint.hip
   int adj_ntx;             // tiles per image row
   const int* adj_off;      // [tiles + 1] first pass of each tile
   const int4* adj_pass;    // [passes][3] header of each pass
-  const int4* adj_ray;     // [ray slots] (t, first rho, last rho, first segment) per slot
+  const int4* adj_ray;     // [ray slots] (t, first rho, last rho, segment numbers) per slot
 };
 
 }  // namespace rl
@@ -155,7 +156,7 @@ constexpr int theta_k1(int k_theta) { return k_theta <= 32 ? k_theta : 32; }
 std::vector<int4> build_fwd_boxes(const DevPlan& d, const std::vector<double2>& cs,
                                   const std::vector<int2>& fq, const std::vector<double>& erho);
 // Plan time (host): the forward's tile lists (small-patch tiles first; their count in *n_small).
-std::vector<int> build_fwd_tiles(const std::vector<int4>& boxes, int* n_small, int* n_mid);
+std::vector<int> build_fwd_tiles(const DevPlan& d, const std::vector<int4>& boxes, int* n_small, int* n_mid);
 // The operator chains behind radon_fwd and radon_adj / radon_transpose / fbp (arguments
 // checked by the caller; ws holds workspace_layout(plan, batch, RL_OP_FWD or op)).
 rl_status forward_chain(const rl_plan* plan, Slices<const float> img, Slices<float> sino, int batch, void* ws,
