@@ -6,7 +6,7 @@
 //                  along rho
 //   k_theta_conv   (shared with the forward) with the conjugate multiplier
 //   k_irfft_scale  inverse real FFT along rho of every support row, times e^rho (step 5)
-//   k_lp2cart_adj  transpose of steps 3-4: per 64x64 image tile, every fine log-polar
+//   k_lp2cart_adj  transpose of steps 3-4: per 48x48 image tile, every fine log-polar
 //                  sample whose bicubic footprint meets the tile is rebuilt from the coarse
 //                  rows by the decimation filter and spread into LDS with the same 16
 //                  weights the forward gathers with; partitions are summed in the tile
@@ -152,8 +152,12 @@ constexpr int kAHalo = 4;       // halo of the LDS tile: footprints reach 3 pixe
                                 // one more on each side covers the range's rounding
 constexpr int kAW = kTile + 2 * kAHalo;  // LDS tile side
 constexpr int kAP = kAW + 1;             // LDS tile pitch (odd)
-constexpr int kUCap = 5120;     // floats of the LDS copy of the coarse rows a pass reads
-constexpr int kECap = 512;      // rho indices of the LDS copy of e^rho
+constexpr int kUCap = 4096;     // floats of the LDS copy of the coarse rows a pass reads
+constexpr int kECap = 256;      // rho indices of the LDS copy of e^rho
+// The tile side, the two caps and the block's register budget (waves_per_eu below) are sized
+// together: 51.8 KB of LDS and at most 80 VGPRs let three 512-thread blocks share a CU (six
+// waves per SIMD; measured, 53 192 bytes of LDS per block still ran three per CU, 53 384 did
+// not).  64 x 64 tiles (74 KB) ran two blocks per CU, 25% slower.
 
 // In-place exclusive scan of buf[0..nitems), nitems <= 3 * 64, by the first wave alone (no
 // block barriers inside); returns the total to that wave.  Callers synchronise around it.
@@ -814,8 +818,8 @@ rl_status build_adj_passes(rl_plan* p) {
 // window usually covers the pass), and every thread walks at most one segment.  The FP64
 // tile (with its halo) collects all partitions and is written once.
 template <bool BF>
-__global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const float* __restrict__ U,
-                                                              float* __restrict__ cbar) {
+__global__ __launch_bounds__(kAThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_lp2cart_adj(
+    DevPlan P, const float* __restrict__ U, float* __restrict__ cbar) {
   // FP64: LDS float atomics are slow on this target.
   __shared__ double acc[kAW * kAP];
   __shared__ int rq0[kASlots];
@@ -879,7 +883,7 @@ __global__ __launch_bounds__(kAThreads, 4) void k_lp2cart_adj(DevPlan P, const f
     const int rlo = BF ? (cg0 == 0 ? -3 : cg0) : cg0;
     const int rhi = BF ? (cg1 == P.n_sup - 1 ? P.n_sup + 3 : cg1) : cg1;
     const int nur = rhi - rlo + 1;
-    const int wlen = max(4, (min(kECap, kUCap / nur) - 4) & ~3);  // nur <= kARows + 3, so >= 32
+    const int wlen = max(4, (min(kECap, kUCap / nur) - 4) & ~3);  // nur <= kARows / r + 11
     for (int wq = qlo; wq <= qhi; wq += wlen) {
       const int wq4 = wq & ~3;
       const int wend = min(wq + wlen - 1, qhi);  // last rho index walked in this window

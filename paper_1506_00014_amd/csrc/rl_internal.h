@@ -16,7 +16,7 @@ constexpr int kHalo = 2;          // coarse rows on each side of a partition's o
 constexpr int kThreads = 256;     // threads per block of every hot-path kernel
 constexpr int kRowVals = 16;      // complex values per thread in a row FFT (N_rho/2 <= 4096)
 constexpr int kColVals = 32;      // complex values per thread in the theta pass
-constexpr int kTile = 64;         // image tile side of the adjoint splat
+constexpr int kTile = 48;         // image tile side of the adjoint splat
 constexpr int kPrefR = 16;        // half-length of the truncated prefilter (|z|^17 ~ 2e-10)
 constexpr int kMaxPart = 16;      // largest supported M
 
