@@ -104,13 +104,13 @@ __global__ __launch_bounds__(kThreads) void k_irfft_scale(DevPlan P, const float
   const int nc = P.nc;
   const size_t row = blockIdx.x;
   const float2* src = spec + row * P.ld;
-  irfft_pre(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
+  irfft_pre<kChunkSmall>(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
   __syncthreads();
   fft_lds<kRowVals, true>(sh, nc, 1, P.twp_rows);
   const float* x = reinterpret_cast<const float*>(sh);
   float* dst = u + row * P.n_rho;
   const double e_scale = P.a_R * P.dx;
-  row_copy(
+  row_copy<kChunkSmall>(
       P.n_rho, [&](int q) { return P.erho[q]; }, [&](int q, double e) { dst[q] = x[q] * (float)(e * e_scale); });
 }
 

@@ -169,21 +169,23 @@ __device__ __forceinline__ void fft_lds(float2* buf, int N, int nfft, const floa
 // Values a thread handles per chunk in the row loops below.  A loop over a row with a global
 // load per iteration would wait a full memory round trip per iteration (nothing lets the
 // compiler overlap iterations of a loop whose trip count is unknown); these loops issue all
-// loads of a chunk first, then consume them.
+// loads of a chunk first, then consume them.  Fewer values per chunk (kChunkSmall) leave the
+// registers for more waves; which is faster depends on the kernel (measured per kernel).
 constexpr int kChunk = 8;
+constexpr int kChunkSmall = 4;
 
-// For i in [0, n), strided over the block: put(i, get(i)), the gets of a chunk issued together
-// (unconditionally: an index past the end reads entry n - 1, unused, so that no branch splits
-// the loads).  n >= 1.
-template <class Get, class Put>
+// For i in [0, n), strided over the block: put(i, get(i)), the gets of a chunk of CH values
+// per thread issued together (unconditionally: an index past the end reads entry n - 1,
+// unused, so that no branch splits the loads).  n >= 1.
+template <int CH = kChunk, class Get, class Put>
 __device__ __forceinline__ void row_copy(int n, Get get, Put put) {
   using T = decltype(get(0));
-  for (int base = 0; base < n; base += kChunk * (int)blockDim.x) {
-    T v[kChunk];
+  for (int base = 0; base < n; base += CH * (int)blockDim.x) {
+    T v[CH];
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c) v[c] = get(min(base + (int)threadIdx.x + c * (int)blockDim.x, n - 1));
+    for (int c = 0; c < CH; ++c) v[c] = get(min(base + (int)threadIdx.x + c * (int)blockDim.x, n - 1));
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int i = base + (int)threadIdx.x + c * (int)blockDim.x;
       if (i < n) put(i, v[c]);
     }
@@ -193,21 +195,21 @@ __device__ __forceinline__ void row_copy(int n, Get get, Put put) {
 // Real FFT post-processing: Z = FFT_nc(x[2n] + i x[2n+1]) in LDS -> X[k], k = 0..nc, of the
 // length-2nc real signal.  Calls fn(k, X[k]) for every k in [0, nc].  Threads stride over
 // k in [0, nc/2]; each handles k and nc - k.
-template <class Fn>
+template <int CH = kChunk, class Fn>
 __device__ __forceinline__ void rfft_post(const float2* Z, int nc, const float2* __restrict__ tw,
                                           int tw_len, Fn fn) {
   const int step = tw_len / (2 * nc);
   const int half = nc / 2;
-  for (int base = 0; base <= half; base += kChunk * (int)blockDim.x) {
-    float2 w1[kChunk], w2[kChunk];
+  for (int base = 0; base <= half; base += CH * (int)blockDim.x) {
+    float2 w1[CH], w2[CH];
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c) {  // twiddles of the chunk (global) first, unconditionally
+    for (int c = 0; c < CH; ++c) {  // twiddles of the chunk (global) first, unconditionally
       const int k = min(base + (int)threadIdx.x + c * (int)blockDim.x, half);
       w1[c] = tw[k * step];
       w2[c] = tw[(nc - k) * step];  // k = 0: exp(-i pi) = -1
     }
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int k = base + (int)threadIdx.x + c * (int)blockDim.x;
       if (k > half) continue;
       const int km = nc - k;
@@ -232,21 +234,21 @@ __device__ __forceinline__ void rfft_post(const float2* Z, int nc, const float2*
 // Inverse real FFT pre-processing: X[k], k = 0..nc (read through get(k)) -> Z[k], k < nc,
 // such that the unnormalised inverse FFT_nc of Z gives z[n] = y[2n] + i y[2n+1] where y is
 // the unnormalised inverse DFT of length 2nc of the Hermitian extension of X.
-template <class Get>
+template <int CH = kChunk, class Get>
 __device__ __forceinline__ void irfft_pre(float2* Z, int nc, const float2* __restrict__ tw,
                                           int tw_len, Get get) {
   const int step = tw_len / (2 * nc);
-  for (int base = 0; base < nc; base += kChunk * (int)blockDim.x) {
-    float2 xa[kChunk], xb[kChunk], w[kChunk];
+  for (int base = 0; base < nc; base += CH * (int)blockDim.x) {
+    float2 xa[CH], xb[CH], w[CH];
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c) {  // every load of the chunk first, unconditionally
+    for (int c = 0; c < CH; ++c) {  // every load of the chunk first, unconditionally
       const int k = min(base + (int)threadIdx.x + c * (int)blockDim.x, nc - 1);
       xa[c] = get(k);
       xb[c] = get(nc - k);
       w[c] = tw[k * step];
     }
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int k = base + (int)threadIdx.x + c * (int)blockDim.x;
       if (k >= nc) continue;
       const float2 a = xa[c];

@@ -535,11 +535,11 @@ __global__ __launch_bounds__(kThreads) void k_rfft_rows(DevPlan P, const float* 
   const int nc = P.nc;
   const size_t row = blockIdx.x;
   const float2* src = reinterpret_cast<const float2*>(in + row * P.n_rho);
-  row_copy(nc, [&](int i) { return src[i]; }, [&](int i, float2 v) { sh[i] = v; });
+  row_copy<kChunkSmall>(nc, [&](int i) { return src[i]; }, [&](int i, float2 v) { sh[i] = v; });
   __syncthreads();
   fft_lds<kRowVals, false>(sh, nc, 1, P.twp_rows);
   float2* dst = out + row * P.ld;
-  rfft_post(sh, nc, P.tw, P.tw_len, [&](int k, float2 x) { dst[k] = x; });
+  rfft_post<kChunkSmall>(sh, nc, P.tw, P.tw_len, [&](int k, float2 x) { dst[k] = x; });
 }
 
 rl_status launch_rfft_rows(const rl_plan* p, const float* in, float2* out, int rows, hipStream_t s) {
@@ -768,14 +768,14 @@ __global__ __launch_bounds__(kThreads) void k_irfft_eval(DevPlan P, const float2
   const int j = jw & ((1 << 30) - 1);
   const int nc = P.nc, nr = P.n_rho;
   const float2* src = spec + ((size_t)bm * P.n_own + o) * P.ld;
-  irfft_pre(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
+  irfft_pre<kChunkSmall>(sh, nc, P.tw, P.tw_len, [&](int k) { return src[k]; });
   __syncthreads();
   fft_lds<kRowVals, true>(sh, nc, 1, P.twp_rows);
   const float* x = reinterpret_cast<const float*>(sh);
   const float inv_aR = (float)(scale / (6.0 * P.a_R));  // 1/a_R, the weights' 1/6, the output scale
   float* __restrict__ dst = sino.at(b) + (size_t)j * P.n_s;
   const int2* tr = P.tau + ((size_t)m * P.n_own + o) * P.n_s;  // rho position of each sample
-  row_copy(
+  row_copy<kChunkSmall>(
       P.n_s, [&](int k) { return tr[k]; },
       [&](int k, int2 t) {
         float w[4];
