@@ -474,7 +474,7 @@ __device__ __forceinline__ void add_block(double* acc, int i0, const Row4& r0, c
 
 template <int SX, int SY>
 __device__ __forceinline__ void splat_walk_fixed(const SegWalk2& sw, double* acc, const float* rows, int rstride,
-                                                 const double* erho, int qlo) {
+                                                 const double* erho, int qlo, double eratio) {
   if (sw.qend < sw.qbeg) return;
   constexpr int CS = SX, RS = SY * kAP;
   Row4 r0 = {0.f, 0.f, 0.f, 0.f}, r1 = r0, r2 = r0, r3 = r0;
@@ -487,8 +487,13 @@ __device__ __forceinline__ void splat_walk_fixed(const SegWalk2& sw, double* acc
   }
   int ci = sw.obase + CS * (ckx - 1) + RS * (cky - 1);  // element of the trailing corner
   const float* rp = rows + (sw.qbeg - qlo) * rstride + sw.rrow;
+  // e^rho of the next step by one product (eratio = e^{Delta rho}) instead of an LDS read:
+  // a read issued after the previous step's adds would wait for them (LDS operations of a
+  // wave complete in order); over a segment the product drifts by ~1e-14 relative
+  double Er = erho[sw.qbeg - qlo];
   for (int q = sw.qbeg; q <= sw.qend; ++q, rp += rstride) {
-    const double E = erho[q - qlo];
+    const double E = Er;
+    Er *= eratio;
     const float V = sw.dw[0] * rp[0] + sw.dw[1] * rp[1] + sw.dw[2] * rp[2] + sw.dw[3] * rp[3];
     const double X = sw.X0 + E * sw.cx, Y = sw.Y0 + E * sw.cy;
     const double fx = floor(X), fy = floor(Y);
@@ -837,6 +842,7 @@ __global__ __launch_bounds__(kAThreads) __attribute__((amdgpu_waves_per_eu(6, 8)
   const int n = P.n, r = P.r;
   const int tx0 = blockIdx.x * kTile, ty0 = blockIdx.y * kTile;
   const int b = blockIdx.z;
+  const double eratio = exp(P.d_rho);  // ratio of consecutive e^rho
   const int tile = blockIdx.y * P.adj_ntx + blockIdx.x;
   for (int i = threadIdx.x; i < kAW * kAP; i += blockDim.x) acc[i] = 0.0;
   const int txe = min(tx0 + kTile, n), tye = min(ty0 + kTile, n);
@@ -975,11 +981,11 @@ __global__ __launch_bounds__(kAThreads) __attribute__((amdgpu_waves_per_eu(6, 8)
             const bool wx = __builtin_amdgcn_readfirstlane((int)xp) != 0;
             const bool wy = __builtin_amdgcn_readfirstlane((int)yp) != 0;
             if (wx) {
-              if (wy) splat_walk_fixed<1, 1>(sw, acc, us, nur, es, wq4);
-              else splat_walk_fixed<1, -1>(sw, acc, us, nur, es, wq4);
+              if (wy) splat_walk_fixed<1, 1>(sw, acc, us, nur, es, wq4, eratio);
+              else splat_walk_fixed<1, -1>(sw, acc, us, nur, es, wq4, eratio);
             } else {
-              if (wy) splat_walk_fixed<-1, 1>(sw, acc, us, nur, es, wq4);
-              else splat_walk_fixed<-1, -1>(sw, acc, us, nur, es, wq4);
+              if (wy) splat_walk_fixed<-1, 1>(sw, acc, us, nur, es, wq4, eratio);
+              else splat_walk_fixed<-1, -1>(sw, acc, us, nur, es, wq4, eratio);
             }
           } else {
             splat_walk_bf(sw, acc, us, nur, es, wq4);
