@@ -158,6 +158,9 @@ constexpr int kECap = 256;      // rho indices of the LDS copy of e^rho
 // together: 51.8 KB of LDS and at most 80 VGPRs let three 512-thread blocks share a CU (six
 // waves per SIMD; measured, 53 192 bytes of LDS per block still ran three per CU, 53 384 did
 // not).  64 x 64 tiles (74 KB) ran two blocks per CU, 25% slower.
+constexpr int kSplatLds = 8 * kAW * kAP + 4 * (5 * kASlots + 1) + 2 * 16 * kASlots + 4 * kUCap + 8 * kECap +
+                          2 * kAThreads;  // the splat's __shared__ arrays, in bytes
+static_assert(kSplatLds + 256 <= 53248, "the splat's LDS must leave room for three blocks per CU");
 
 // In-place exclusive scan of buf[0..nitems), nitems <= 3 * 64, by the first wave alone (no
 // block barriers inside); returns the total to that wave.  Callers synchronise around it.
