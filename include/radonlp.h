@@ -109,9 +109,10 @@ typedef struct {
 
 typedef struct rl_plan rl_plan;
 
-/* Execution-only launch parameters of a plan.  None of them changes any result: every output
- * value is computed by the same arithmetic in the same order whatever they are, so results are
- * bitwise identical for every setting; they only change block shapes and schedules.
+/* Execution-only launch parameters of a plan.  They change block shapes and schedules, not the
+ * operator: with every setting of the first five, every output value is computed by the same
+ * arithmetic in the same order (bitwise identical results); adj_walk changes R#'s rounding only
+ * (see below).
  *   theta_cols       spectrum columns per block of the theta-convolution pass (1 .. 8, capped
  *                    at 256 / the larger factor of k_theta; 0 = the largest allowed)
  *   theta_xcd_order  1: blocks of the theta pass are ordered so that neighbouring column strips
@@ -126,8 +127,9 @@ typedef struct rl_plan rl_plan;
  *   adj_walk         walk of the back-projection's Cartesian splat (both sum each sample's 16
  *                    weighted values in a register footprint that follows the ray and add what it
  *                    leaves behind to the LDS tile): 0 moves the footprint under branches, 1 moves
- *                    it by selects every step (uniform across a wave).  The two add the same FP32
- *                    terms in FP64 in a different order.
+ *                    it by selects every step (uniform across a wave) and takes e^rho along the
+ *                    ray by a running product.  The two add the same FP32 terms up to the last
+ *                    bits of the FP64 sample positions, in FP64, in a different order.
  * Defaults (rl_plan_create): 0, 1, 512, 1, 1, 1. */
 typedef struct {
   int32_t theta_cols;
