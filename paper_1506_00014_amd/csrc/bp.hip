@@ -139,7 +139,6 @@ __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* 
   const int nb = min(kBch, batch - b0);
   const bool in_img = ix < P.n && iy < P.n;
   const bool act = in_img && in_unit_disc(ix, iy, P.n);
-  const double x1 = -1.0 + ix * P.dx, x2 = -1.0 + iy * P.dx;
   const int nr = P.n_rho;
   const size_t slice = (size_t)P.m * P.n_sup * nr;  // lattice floats of one slice
   float acc[kBch];
@@ -155,21 +154,14 @@ __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* 
     }
     int kt = 1, kr = 0;
     float wt[4], wr[4];
-    if (act) {
-      double sm, cm;
-      sincospi((double)m / (double)P.m, &sm, &cm);
-      // y = T_m x = a_R Rot(-m beta) x + (1 - a_R, 0) (eq. Tdef)
-      const double y1 = P.a_R * (cm * x1 + sm * x2) + (1.0 - P.a_R);
-      const double y2 = P.a_R * (cm * x2 - sm * x1);
-      const double T = (atan2(y2, y1) - P.phi0[m]) / P.dtheta;
-      const double R = (0.5 * log(y1 * y1 + y2 * y2) - P.rho0) / P.d_rho;
-      const double ft = floor(T), fr = floor(R);
-      bspline_w6((float)(T - ft), wt);
-      bspline_w6((float)(R - fr), wr);
-      // |x| < 1 puts T in [1, n_own + 2) and R in [-1, n_rho - 1] (T_m maps the unit disc
-      // onto D); the clamps only guard the loads
-      kt = min(max((int)ft, 1), P.n_sup - 3);
-      kr = min(max((int)fr, -1), nr - 1);
+    if (act) {  // the lattice coordinates of T_m x, built with the plan (k_bp_geometry)
+      const size_t gi = ((size_t)m * P.n + iy) * P.n + ix;
+      const unsigned kk = P.bp_k[gi];
+      const float2 fr = P.bp_f[gi];
+      kt = (int)(kk >> 16);
+      kr = (int)(kk & 0xffffu) - 1;
+      bspline_w6(fr.x, wt);
+      bspline_w6(fr.y, wr);
     }
     const float* L0 = lat + (size_t)(b0 * P.m + m) * P.n_sup * nr;  // row 0 of partition m, slice b0
     int r0 = 0, nrow = 0, c0 = 0, ncol = 0;
@@ -248,6 +240,46 @@ __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* 
     for (int bb = 0; bb < kBch; ++bb)
       if (bb < nb) img.at(b0 + bb)[(size_t)iy * P.n + ix] = acc[bb] * (1.0f / 36.0f);
   }
+}
+
+// Plan time: the lattice coordinates of T_m x for every pixel x in the unit disc (Alg. 2 step 5):
+// y = T_m x = a_R Rot(-m beta) x + (1 - a_R, 0) (eq. Tdef) at angle position T = (atan2(y) -
+// phi0_m) / dtheta and log-radius position R = (log |y| - rho0) / d_rho; the gather's 4 x 4 taps
+// start one before floor(T), floor(R), with weights from the fractions past them.  |x| < 1 puts
+// T in [1, n_own + 2) and R in [-1, n_rho - 1] (T_m maps the unit disc onto D); the clamps only
+// guard the gather's loads.
+__global__ __launch_bounds__(kThreads) void k_bp_geometry(DevPlan P, unsigned* __restrict__ kout,
+                                                          float2* __restrict__ fout) {
+  const int ix = blockIdx.x * kGx + (int)threadIdx.x % kGx, iy = blockIdx.y * kGy + (int)threadIdx.x / kGx;
+  const int m = blockIdx.z;
+  if (ix >= P.n || iy >= P.n) return;
+  unsigned kk = (1u << 16) | 1u;  // (pixels outside the disc are never read)
+  float2 fr = make_float2(0.f, 0.f);
+  if (in_unit_disc(ix, iy, P.n)) {
+    const double x1 = -1.0 + ix * P.dx, x2 = -1.0 + iy * P.dx;
+    double sm, cm;
+    sincospi((double)m / (double)P.m, &sm, &cm);
+    const double y1 = P.a_R * (cm * x1 + sm * x2) + (1.0 - P.a_R);
+    const double y2 = P.a_R * (cm * x2 - sm * x1);
+    const double T = (atan2(y2, y1) - P.phi0[m]) / P.dtheta;
+    const double R = (0.5 * log(y1 * y1 + y2 * y2) - P.rho0) / P.d_rho;
+    const double ft = floor(T), fq = floor(R);
+    const int kt = min(max((int)ft, 1), P.n_sup - 3);
+    const int kr = min(max((int)fq, -1), P.n_rho - 1);
+    kk = ((unsigned)kt << 16) | (unsigned)(kr + 1);
+    fr = make_float2((float)(T - ft), (float)(R - fq));
+  }
+  const size_t gi = ((size_t)m * P.n + iy) * P.n + ix;
+  kout[gi] = kk;
+  fout[gi] = fr;
+}
+
+rl_status build_bp_geometry(const DevPlan& d, unsigned* k, float2* f) {
+  if (d.n_sup - 3 >= (1 << 16) || d.n_rho + 1 >= (1 << 16))
+    return fail(RL_ERR_GEOMETRY, "lattice too large for the packed gather coordinates");
+  hipLaunchKernelGGL(k_bp_geometry, dim3((d.n + kGx - 1) / kGx, (d.n + kGy - 1) / kGy, d.m), dim3(kThreads), 0, 0, d,
+                     k, f);
+  return check_launch("k_bp_geometry");
 }
 
 rl_status prepare_bp_launches(const rl_plan* p) {

@@ -59,6 +59,10 @@ struct DevPlan {
   const float* ramp;       // [3][lr/2 + 1] filter multipliers (rl_filter order), include 1/lr
   const float* pref;       // [kPrefR + 1] prefilter taps sqrt(3) z^|k|
   const double* erho;      // [n_rho] e^{rho_q} / (a_R dx): image-index length of the ray at rho_q
+  const unsigned* bp_k;    // [m][n][n] Algorithm 2's gather: lattice tap base of T_m x for each
+                           // pixel in the unit disc, row (clamped to [1, n_sup - 3]) << 16 |
+                           // column + 1 (column clamped to [-1, n_rho - 1])
+  const float2* bp_f;      // [m][n][n] the fractions of T_m x past those bases (theta, rho)
   const int2* tau;         // [m][n_own][n_s] rho position tau of S_m(theta_j, s_k) on each owned
                            // row: (floor(tau) clamped to [-1, n_rho], bits of the FP32 fraction)
   const float* dtap;       // [4r - 1] decimation taps d_n, n = -(2r-1) .. 2r-1
@@ -172,6 +176,8 @@ rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int b
                      rl_op op);
 // Plan time: raise the LDS limit of the Algorithm 2 row kernel (bp.hip).
 rl_status prepare_bp_launches(const rl_plan* p);
+// Plan time: fill DevPlan::bp_k and bp_f (Algorithm 2's per-pixel lattice coordinates).
+rl_status build_bp_geometry(const DevPlan& d, unsigned* k, float2* f);
 // Workspace of rl_em / rl_em_norm (em.hip).
 size_t em_workspace_bytes(const rl_plan* plan, int batch);
 // Set the plan's launch parameters from the autotuner cache at `path` (tune.hip): false if the
