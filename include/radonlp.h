@@ -176,7 +176,7 @@ rl_status rl_geom_default(int32_t n, int32_t n_theta, int32_t n_s, int32_t m, in
  * computed in FP64 by composite Gauss-Legendre quadrature on the device, and FFT
  * twiddles.  Synchronous and allowed to be slow; not part of any timed path.  The plan
  * owns its device tables (about 12 m n^2 bytes, the per-pixel coordinates Algorithm 2 reads,
- * plus ~60 MB at n = 2048), is immutable after creation and may be used from several
+ * plus about 70 MB at n = 2048), is immutable after creation and may be used from several
  * streams at once.  On failure *out is set to NULL. */
 rl_status rl_plan_create(const rl_geom* geom, rl_plan** out);
 
