@@ -131,7 +131,6 @@ template <bool STAGED>
 __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* __restrict__ lat,
                                                         Slices<float> img, int batch) {
   __shared__ float box[STAGED ? kBch : 1][STAGED ? kBox : 1];
-  __shared__ int red[2][4];  // per partition parity: min/max row base, min/max column base
   const int t = (int)threadIdx.x, wv = t >> 6, ln = t & 63;
   const int ix = blockIdx.x * kGx + (ln & 7) + 8 * (wv & 1);
   const int iy = blockIdx.y * kGy + (ln >> 3) + 8 * (wv >> 1);
@@ -145,13 +144,6 @@ __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* 
 #pragma unroll
   for (int bb = 0; bb < kBch; ++bb) acc[bb] = 0.f;
   for (int m = 0; m < P.m; ++m) {
-    int* rd = red[m & 1];  // the other parity was last read before the previous barriers
-    if (STAGED && t == 0) {
-      rd[0] = INT_MAX;
-      rd[1] = INT_MIN;
-      rd[2] = INT_MAX;
-      rd[3] = INT_MIN;
-    }
     int kt = 1, kr = 0;
     float wt[4], wr[4];
     if (act) {  // the lattice coordinates of T_m x, built with the plan (k_bp_geometry)
@@ -166,28 +158,14 @@ __global__ __launch_bounds__(kThreads) void k_bp_gather(DevPlan P, const float* 
     const float* L0 = lat + (size_t)(b0 * P.m + m) * P.n_sup * nr;  // row 0 of partition m, slice b0
     int r0 = 0, nrow = 0, c0 = 0, ncol = 0;
     if (STAGED) {
-      __syncthreads();  // the reset of rd is visible; the previous partition's box reads are done
-      // reduce across the wave first (inactive lanes hold neutral values), one atomic per wave
-      int lo_t = act ? kt : INT_MAX, hi_t = act ? kt : INT_MIN, lo_r = act ? kr : INT_MAX, hi_r = act ? kr : INT_MIN;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        lo_t = min(lo_t, __shfl_xor(lo_t, off));
-        hi_t = max(hi_t, __shfl_xor(hi_t, off));
-        lo_r = min(lo_r, __shfl_xor(lo_r, off));
-        hi_r = max(hi_r, __shfl_xor(hi_r, off));
-      }
-      if (ln == 0 && lo_t <= hi_t) {
-        atomicMin(&rd[0], lo_t);
-        atomicMax(&rd[1], hi_t);
-        atomicMin(&rd[2], lo_r);
-        atomicMax(&rd[3], hi_r);
-      }
-      __syncthreads();
-      if (rd[0] > rd[1]) continue;  // no pixel of the tile in the disc (uniform)
-      r0 = rd[0] - 1;
-      nrow = rd[1] - rd[0] + 4;
-      c0 = rd[2] - 1;
-      ncol = rd[3] - rd[2] + 4;
+      // the tile's lattice box, built with the plan
+      const int4 bb = P.bp_box[(size_t)m * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x];
+      if (bb.y == 0) continue;  // no pixel of the tile in the disc (uniform)
+      __syncthreads();  // the previous partition's box reads are done
+      r0 = bb.x;
+      nrow = bb.y;
+      c0 = bb.z;
+      ncol = bb.w;
     }
     if (STAGED && nrow * ncol <= kBox) {  // uniform
       const int nbox = nrow * ncol;
@@ -274,12 +252,49 @@ __global__ __launch_bounds__(kThreads) void k_bp_geometry(DevPlan P, unsigned* _
   fout[gi] = fr;
 }
 
-rl_status build_bp_geometry(const DevPlan& d, unsigned* k, float2* f) {
+// Plan time: each gather tile's lattice box for partition m, from the coordinates above: rows
+// min kt - 1 .. max kt + 2 and columns min kr - 1 .. max kr + 2 over its pixels in the disc.
+__global__ __launch_bounds__(kThreads) void k_bp_boxes(DevPlan P, const unsigned* __restrict__ kin,
+                                                       int4* __restrict__ box) {
+  __shared__ int red[4];
+  const int t = (int)threadIdx.x, ln = t & 63, wv = t >> 6;
+  const int ix = blockIdx.x * kGx + (ln & 7) + 8 * (wv & 1);
+  const int iy = blockIdx.y * kGy + (ln >> 3) + 8 * (wv >> 1);
+  const int m = blockIdx.z;
+  if (t == 0) {
+    red[0] = INT_MAX;
+    red[1] = INT_MIN;
+    red[2] = INT_MAX;
+    red[3] = INT_MIN;
+  }
+  __syncthreads();
+  if (ix < P.n && iy < P.n && in_unit_disc(ix, iy, P.n)) {
+    const unsigned kk = kin[((size_t)m * P.n + iy) * P.n + ix];
+    const int kt = (int)(kk >> 16), kr = (int)(kk & 0xffffu) - 1;
+    atomicMin(&red[0], kt);
+    atomicMax(&red[1], kt);
+    atomicMin(&red[2], kr);
+    atomicMax(&red[3], kr);
+  }
+  __syncthreads();
+  if (t == 0) {
+    const int4 b = red[0] > red[1] ? make_int4(0, 0, 0, 0)
+                                   : make_int4(red[0] - 1, red[1] - red[0] + 4, red[2] - 1, red[3] - red[2] + 4);
+    box[((size_t)m * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = b;
+  }
+}
+
+int bp_tiles(int n) { return ((n + kGx - 1) / kGx) * ((n + kGy - 1) / kGy); }
+
+rl_status build_bp_geometry(const DevPlan& d, unsigned* k, float2* f, int4* box) {
   if (d.n_sup - 3 >= (1 << 16) || d.n_rho + 1 >= (1 << 16))
     return fail(RL_ERR_GEOMETRY, "lattice too large for the packed gather coordinates");
-  hipLaunchKernelGGL(k_bp_geometry, dim3((d.n + kGx - 1) / kGx, (d.n + kGy - 1) / kGy, d.m), dim3(kThreads), 0, 0, d,
-                     k, f);
-  return check_launch("k_bp_geometry");
+  const dim3 grid((d.n + kGx - 1) / kGx, (d.n + kGy - 1) / kGy, d.m);
+  hipLaunchKernelGGL(k_bp_geometry, grid, dim3(kThreads), 0, 0, d, k, f);
+  rl_status st = check_launch("k_bp_geometry");
+  if (st != RL_OK) return st;
+  hipLaunchKernelGGL(k_bp_boxes, grid, dim3(kThreads), 0, 0, d, k, box);
+  return check_launch("k_bp_boxes");
 }
 
 rl_status prepare_bp_launches(const rl_plan* p) {

@@ -612,6 +612,7 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   const size_t n_px = (size_t)M * g.n * g.n;  // Algorithm 2's per-pixel lattice coordinates
   const size_t o_bk = off; off += al(sizeof(unsigned) * n_px);
   const size_t o_bf = off; off += al(sizeof(float2) * n_px);
+  const size_t o_bb = off; off += al(sizeof(int4) * (size_t)M * bp_tiles(g.n));
   const size_t table_bytes = off;
   // scratch for the quadrature (freed before returning)
   const size_t s_u = 0, s_a = al(sizeof(double) * n_nodes_pad), s_l = 2 * s_a, s_a2 = 3 * s_a, s_l2 = 4 * s_a;
@@ -736,9 +737,10 @@ extern "C" rl_status rl_plan_create(const rl_geom* geom, rl_plan** out) {
   d.ftiles_large = (int)ftiles.size() - n_small_tiles - n_mid_tiles;
   d.bp_k = (const unsigned*)(mem + o_bk);
   d.bp_f = (const float2*)(mem + o_bf);
+  d.bp_box = (const int4*)(mem + o_bb);
   hipLaunchKernelGGL(k_tau_table, dim3(n_own, M), dim3(256), 0, 0, d, (int2*)(mem + o_ta));
   if ((st = check_launch("k_tau_table")) != RL_OK) return cleanup(st);
-  if ((st = build_bp_geometry(d, (unsigned*)(mem + o_bk), (float2*)(mem + o_bf))) != RL_OK) return cleanup(st);
+  if ((st = build_bp_geometry(d, (unsigned*)(mem + o_bk), (float2*)(mem + o_bf), (int4*)(mem + o_bb))) != RL_OK) return cleanup(st);
   if ((st = check_hip(hipDeviceSynchronize(), "k_tau_table")) != RL_OK) return cleanup(st);
   plan->d_mem = mem;
   plan->d_mem_bytes = table_bytes;

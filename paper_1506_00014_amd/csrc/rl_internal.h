@@ -63,6 +63,9 @@ struct DevPlan {
                            // pixel in the unit disc, row (clamped to [1, n_sup - 3]) << 16 |
                            // column + 1 (column clamped to [-1, n_rho - 1])
   const float2* bp_f;      // [m][n][n] the fractions of T_m x past those bases (theta, rho)
+  const int4* bp_box;      // [m][gather tiles] lattice box (first row, rows, first column,
+                           // columns) the 4 x 4 taps of a 16 x 16-pixel tile's pixels in the
+                           // unit disc read; rows = 0: the tile has no such pixel
   const int2* tau;         // [m][n_own][n_s] rho position tau of S_m(theta_j, s_k) on each owned
                            // row: (floor(tau) clamped to [-1, n_rho], bits of the FP32 fraction)
   const float* dtap;       // [4r - 1] decimation taps d_n, n = -(2r-1) .. 2r-1
@@ -177,7 +180,9 @@ rl_status adj_checks(const rl_plan* plan, const void* in, const void* out, int b
 // Plan time: raise the LDS limit of the Algorithm 2 row kernel (bp.hip).
 rl_status prepare_bp_launches(const rl_plan* p);
 // Plan time: fill DevPlan::bp_k and bp_f (Algorithm 2's per-pixel lattice coordinates).
-rl_status build_bp_geometry(const DevPlan& d, unsigned* k, float2* f);
+rl_status build_bp_geometry(const DevPlan& d, unsigned* k, float2* f, int4* box);
+// Gather tiles of Algorithm 2 (16 x 16 pixels) for an n x n image.
+int bp_tiles(int n);
 // Workspace of rl_em / rl_em_norm (em.hip).
 size_t em_workspace_bytes(const rl_plan* plan, int batch);
 // Set the plan's launch parameters from the autotuner cache at `path` (tune.hip): false if the
