@@ -122,9 +122,10 @@ __global__ __launch_bounds__(kThreads) void k_bp_rows_rfft(DevPlan P, Slices<con
 
 // Block: 16 x 16 pixels (each wave an 8 x 8 sub-tile) of kBch slices.  lat holds the support
 // rows [batch][m][n_sup][n_rho] of the convolved lattice (spline coefficients); support row
-// kHalo is a partition's first owned row.  Per partition the block finds the lattice box its
-// pixels' taps cover; if it fits kBox floats, the box of each slice is staged in LDS with
-// coalesced loads and the 16 taps are read there, otherwise they are read from global memory.
+// kHalo is a partition's first owned row.  Per partition the pixels' lattice coordinates and
+// the box their taps cover come from the plan (k_bp_geometry, k_bp_boxes); if the box fits kBox
+// floats, the box of each slice is staged in LDS with coalesced loads and the 16 taps are read
+// there, otherwise they are read from global memory.
 // STAGED = false reads every tap from global memory (no LDS, no barriers): calls with fewer
 // than kStageMin slices gain nothing from the staging and lose occupancy to its LDS.
 template <bool STAGED>
