@@ -843,11 +843,13 @@ __global__ __launch_bounds__(kAThreads) __attribute__((amdgpu_waves_per_eu(6, 8)
   // the segment length so that every thread walks at most one)
   __shared__ short segslot[kAThreads];
   const int n = P.n, r = P.r;
-  // (tile, slice) of this block: each XCD takes one contiguous run of them in slice, tile-row,
-  // tile order, so that neighbouring tiles, which copy overlapping coarse rows, share its L2
-  // (HBM fetch 5.1 -> 2.2 GB per launch of 64 slices at 2048^2)
+  // (tile, slice) of this block: with at least one slice per XCD, each XCD takes one contiguous
+  // run of them in slice, tile-row, tile order, so that neighbouring tiles, which copy
+  // overlapping coarse rows, share its L2 (HBM fetch 5.1 -> 2.2 GB per launch of 64 slices at
+  // 2048^2); with fewer slices, runs of one image's tiles would give the XCDs unequal work
   const int nbt = gridDim.x * gridDim.y;
-  const int lid = xcd_block((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x, nbt * gridDim.z);
+  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int lid = gridDim.z >= kXcds ? xcd_block(bid, nbt * gridDim.z) : bid;
   const int b = lid / nbt, tl = lid - b * nbt;
   const int tyi = tl / gridDim.x, txi = tl - tyi * gridDim.x;
   const int tx0 = txi * kTile, ty0 = tyi * kTile;
