@@ -12,8 +12,6 @@
 //                  S_m(theta_j, s_k) (eq. Sm_def, Radon_all_pb; Alg. 1 step 7), times 1/a_R
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
-
 #include "fft_device.h"
 #include "rl_internal.h"
 
@@ -521,14 +519,6 @@ std::vector<int> build_fwd_tiles(const DevPlan& d, const std::vector<int4>& boxe
         }
         lists[cls].push_back(t0);
       }
-  // within each list, blocks whose image boxes lie close together (of any partition) are
-  // adjacent, so that the XCD running them finds most of their pixels in its L2 (small list:
-  // HBM fetch 1.5 -> 0.5 GB per launch of 64 slices at 2048^2); blocks with no sample in D last
-  auto key = [&](int tb) -> long {
-    const int4 b = boxes[tb];
-    return b.z == 0 ? (1L << 40) : ((long)((b.y + b.w / 2) >> 6) << 20) + ((b.x + b.z / 2) >> 6);
-  };
-  for (auto& L : lists) std::stable_sort(L.begin(), L.end(), [&](int a, int b) { return key(a) < key(b); });
   *n_small = (int)lists[0].size();
   *n_mid = (int)lists[1].size();
   std::vector<int> out = lists[0];
